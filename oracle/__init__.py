@@ -1,0 +1,161 @@
+"""CPU complex128 oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only `tests/`, the smoke check in `__graft_entry__` and the CPU-baseline leg
+of `bench.py` may import this package. The GPU library
+(`paper_1801_01037_amd`) never imports it and shares no code with it; the only
+thing both sides read is the serialized gate list from `qcircuits`.
+
+Two tiers:
+  * stride tier (`sv_oracle.c`, plain C): the paper's Algorithm 1 loops, gate
+    by gate, at any n that fits host memory;
+  * brute-force tier (`oracle.dense`, numpy): dense Kronecker-product
+    operators for n <= 10 (the paper's direct approach).
+Closed forms used as pins or as sampled references at large n:
+  * `qft_basis_amplitude` (QFT of |x>), `product_state_amplitude` (circuits
+    of one-qubit gates only, equation circuit-level), `uniform_amplitude`
+    (H on every qubit of |0...0>).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+_lib = None
+
+
+def load(path: str):
+    """Opens a built oracle library and declares its C signatures."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_init_basis.argtypes = [dp, ctypes.c_int, ctypes.c_uint64]
+    L.orc_apply_1q.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_apply_ctrl.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_apply_cphase.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double]
+    L.orc_run_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
+    L.orc_run_circuit.restype = ctypes.c_int
+    L.orc_probs.argtypes = [dp, ctypes.c_uint64, ctypes.c_uint64, dp]
+    L.orc_norm.argtypes = [dp, ctypes.c_int]
+    L.orc_norm.restype = ctypes.c_double
+    L.orc_qft_basis_amplitude.argtypes = [ctypes.c_int, ctypes.c_uint64,
+                                          ctypes.c_uint64, dp]
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(build_oracle.LIB):
+            build_oracle.build()
+        _lib = load(build_oracle.LIB)
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check_state(psi: np.ndarray) -> int:
+    if psi.dtype != np.complex128 or not psi.flags.c_contiguous:
+        raise TypeError("oracle states are C-contiguous complex128 arrays")
+    n = int(psi.size).bit_length() - 1
+    if psi.size != 1 << n:
+        raise ValueError("state length must be a power of two")
+    return n
+
+
+def basis_state(n: int, x: int = 0) -> np.ndarray:
+    psi = np.empty(1 << n, dtype=np.complex128)
+    lib().orc_init_basis(_dp(psi.view(np.float64)), n, x)
+    return psi
+
+
+def apply_1q(psi: np.ndarray, t: int, m) -> None:
+    n = _check_state(psi)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    lib().orc_apply_1q(_dp(psi.view(np.float64)), n, t, _dp(m))
+
+
+def apply_ctrl(psi: np.ndarray, c: int, t: int, m) -> None:
+    n = _check_state(psi)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    lib().orc_apply_ctrl(_dp(psi.view(np.float64)), n, c, t, _dp(m))
+
+
+def apply_cphase(psi: np.ndarray, c: int, t: int, theta: float) -> None:
+    n = _check_state(psi)
+    lib().orc_apply_cphase(_dp(psi.view(np.float64)), n, c, t, float(theta))
+
+
+def run_circuit(psi: np.ndarray, gates: np.ndarray) -> None:
+    """Applies a gate list (qcircuits.GATE_DTYPE records) in place."""
+    n = _check_state(psi)
+    gates = np.ascontiguousarray(gates)
+    rc = lib().orc_run_circuit(_dp(psi.view(np.float64)), n,
+                               gates.ctypes.data, len(gates))
+    if rc != 0:
+        raise ValueError("malformed gate record")
+
+
+def simulate(n: int, gates: np.ndarray, x: int = 0) -> np.ndarray:
+    psi = basis_state(n, x)
+    run_circuit(psi, gates)
+    return psi
+
+
+def probs(psi: np.ndarray, first: int = 0, count: int | None = None) -> np.ndarray:
+    if count is None:
+        count = psi.size - first
+    out = np.empty(count, dtype=np.float64)
+    lib().orc_probs(_dp(psi.view(np.float64)), first, count, _dp(out))
+    return out
+
+
+def norm(psi: np.ndarray) -> float:
+    n = _check_state(psi)
+    return float(lib().orc_norm(_dp(psi.view(np.float64)), n))
+
+
+def qft_basis_amplitude(n: int, x: int, index: int) -> complex:
+    out = np.empty(2)
+    lib().orc_qft_basis_amplitude(n, x, index, _dp(out))
+    return complex(out[0], out[1])
+
+
+def qft_basis_amplitudes(n: int, x: int, indices) -> np.ndarray:
+    return np.array([qft_basis_amplitude(n, x, int(i)) for i in indices])
+
+
+def qubit_vectors(n: int, gates: np.ndarray, x: int = 0) -> np.ndarray:
+    """For a circuit of one-qubit gates only: each qubit's own 2-vector after
+    its gates, starting from bit q of |x> (the product-state rule: a tensor
+    product of gates acts factor by factor, equation circuit-level)."""
+    v = np.zeros((n, 2), dtype=np.complex128)
+    for q in range(n):
+        v[q, (x >> q) & 1] = 1.0
+    for g in gates:
+        if int(g["kind"]) != 0:
+            raise ValueError("product-state rule needs one-qubit gates only")
+        t = int(g["target"])
+        m = g["m"]
+        a, b = v[t]
+        v[t, 0] = complex(m[0], m[1]) * a + complex(m[2], m[3]) * b
+        v[t, 1] = complex(m[4], m[5]) * a + complex(m[6], m[7]) * b
+    return v
+
+
+def product_state_amplitude(vectors: np.ndarray, index: int) -> complex:
+    """alpha_i = prod_q v_q[bit q of i]."""
+    amp = 1.0 + 0.0j
+    for q in range(vectors.shape[0]):
+        amp *= vectors[q, (index >> q) & 1]
+    return amp
+
+
+def uniform_amplitude(n: int) -> float:
+    """Every amplitude of H on each qubit of |0...0>: 2^(-n/2)."""
+    return 2.0 ** (-n / 2)

@@ -1,0 +1,175 @@
+/*
+ * CPU reference state-vector simulator in complex128 -- TEST INFRASTRUCTURE.
+ *
+ * This is the oracle that the GPU library is checked against. Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * GPU library never links, calls or includes it, and the two share no source.
+ *
+ * What it computes (R. LaRose, "Distributed Memory Techniques for Classical
+ * Simulation of Quantum Circuits", arXiv:1801.01037):
+ *   - the state is 2^n complex amplitudes alpha_{b_{n-1}...b_0} (State Vector
+ *     Partitioning, the three-qubit binary-index equation); qubit q is bit q of
+ *     the index, so a gate on qubit q pairs amplitudes 2^q apart (the stride
+ *     rule and the n = 3 pairing figure of the same section);
+ *   - a one-qubit gate Q = [[q11, q12], [q21, q22]] replaces every pair
+ *     (a, b) = (alpha_{..0_i..}, alpha_{..1_i..}) by (q11 a + q12 b,
+ *     q21 a + q22 b)  (the update equation of State Vector Partitioning);
+ *   - it is applied by the two nested loops of Algorithm 1 (Single Node
+ *     Implementation): an outer loop over blocks 2^{i+1} apart and an inner
+ *     loop over the 2^i pairs of a block;
+ *   - a gate with control c and target t runs the same update only on
+ *     amplitudes whose index has bit c set (the caption of Algorithm 1);
+ *   - controlled-phase is the controlled gate with Q = diag(1, e^{i theta}).
+ *
+ * Arithmetic: every complex product is written out in real arithmetic and the
+ * file is built with -ffp-contract=off, so each operation rounds once.
+ * Single-threaded on purpose: it is the plain reference, not a fast path.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define ORC_TWO_PI 6.283185307179586476925286766559
+
+/* Gate record as stored in the serialized gate lists (80 bytes). */
+typedef struct {
+    int32_t kind;     /* 0: 2x2 on target; 1: controlled 2x2; 2: controlled phase */
+    int32_t control;  /* -1 when none */
+    int32_t target;
+    int32_t flags;
+    double m[8];      /* q11, q12, q21, q22 as (re, im); kind 2: m[0] = theta */
+} orc_gate;
+
+enum { ORC_U = 0, ORC_CU = 1, ORC_CPHASE = 2 };
+
+/* psi is interleaved (re, im) doubles, 2^n complex entries. */
+
+/* |x>: every amplitude 0 except alpha_x = 1 (the register starts in a basis
+ * state, |0...0> in the paper's examples). */
+void orc_init_basis(double *psi, int n, uint64_t x)
+{
+    uint64_t N = (uint64_t)1 << n;
+    for (uint64_t i = 0; i < 2 * N; ++i)
+        psi[i] = 0.0;
+    psi[2 * x] = 1.0;
+}
+
+/* One pair update: (a, b) <- (q11 a + q12 b, q21 a + q22 b). */
+static void pair_update(double *a, double *b, const double m[8])
+{
+    double ar = a[0], ai = a[1], br = b[0], bi = b[1];
+    double q11r = m[0], q11i = m[1], q12r = m[2], q12i = m[3];
+    double q21r = m[4], q21i = m[5], q22r = m[6], q22i = m[7];
+    double nar = (q11r * ar - q11i * ai) + (q12r * br - q12i * bi);
+    double nai = (q11r * ai + q11i * ar) + (q12r * bi + q12i * br);
+    double nbr = (q21r * ar - q21i * ai) + (q22r * br - q22i * bi);
+    double nbi = (q21r * ai + q21i * ar) + (q22r * bi + q22i * br);
+    a[0] = nar; a[1] = nai;
+    b[0] = nbr; b[1] = nbi;
+}
+
+/* Algorithm 1: Q on qubit t. Outer loop j over blocks of 2^{t+1} amplitudes,
+ * inner loop k over the first half of the block; k pairs with k + 2^t. */
+void orc_apply_1q(double *psi, int n, int t, const double m[8])
+{
+    uint64_t N = (uint64_t)1 << n;
+    uint64_t stride = (uint64_t)1 << t;
+    for (uint64_t j = 0; j < N; j += 2 * stride)
+        for (uint64_t k = j; k < j + stride; ++k)
+            pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
+}
+
+/* Algorithm 1 with a control qubit c: the same loops, updating only where bit
+ * c of the index is one (c != t, so both members of a pair share bit c). */
+void orc_apply_ctrl(double *psi, int n, int c, int t, const double m[8])
+{
+    uint64_t N = (uint64_t)1 << n;
+    uint64_t stride = (uint64_t)1 << t;
+    uint64_t cbit = (uint64_t)1 << c;
+    for (uint64_t j = 0; j < N; j += 2 * stride)
+        for (uint64_t k = j; k < j + stride; ++k)
+            if (k & cbit)
+                pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
+}
+
+/* Controlled phase: the controlled gate with Q = diag(1, e^{i theta}). */
+void orc_apply_cphase(double *psi, int n, int c, int t, double theta)
+{
+    double m[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, cos(theta), sin(theta)};
+    orc_apply_ctrl(psi, n, c, t, m);
+}
+
+/* Applies the gates in list order. Returns 0, or -1 on a malformed record. */
+int orc_run_circuit(double *psi, int n, const orc_gate *g, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) {
+        int t = g[i].target, c = g[i].control;
+        if (t < 0 || t >= n)
+            return -1;
+        switch (g[i].kind) {
+        case ORC_U:
+            orc_apply_1q(psi, n, t, g[i].m);
+            break;
+        case ORC_CU:
+            if (c < 0 || c >= n || c == t)
+                return -1;
+            orc_apply_ctrl(psi, n, c, t, g[i].m);
+            break;
+        case ORC_CPHASE:
+            if (c < 0 || c >= n || c == t)
+                return -1;
+            orc_apply_cphase(psi, n, c, t, g[i].m[0]);
+            break;
+        default:
+            return -1;
+        }
+    }
+    return 0;
+}
+
+/* p_i = |alpha_i|^2 for i in [first, first + count). */
+void orc_probs(const double *psi, uint64_t first, uint64_t count, double *out)
+{
+    for (uint64_t i = 0; i < count; ++i) {
+        double re = psi[2 * (first + i)], im = psi[2 * (first + i) + 1];
+        out[i] = re * re + im * im;
+    }
+}
+
+/* Pairwise (recursive halving) sum of |alpha_i|^2 over [lo, hi). */
+static double norm_range(const double *psi, uint64_t lo, uint64_t hi)
+{
+    if (hi - lo <= 8) {
+        double s = 0.0;
+        for (uint64_t i = lo; i < hi; ++i)
+            s += psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        return s;
+    }
+    uint64_t mid = lo + (hi - lo) / 2;
+    return norm_range(psi, lo, mid) + norm_range(psi, mid, hi);
+}
+
+/* sum_i |alpha_i|^2, the normalisation of the state (Quantum Information
+ * Processing: the probabilities of a state sum to one). */
+double orc_norm(const double *psi, int n)
+{
+    return norm_range(psi, 0, (uint64_t)1 << n);
+}
+
+/* Closed form of the QFT circuit (no final swaps) on the basis state |x>:
+ * alpha_i = e^{2 pi i x y / 2^n} / 2^{n/2} with y = i with its n bits reversed.
+ * x*y is reduced mod 2^n in 128-bit integers before it becomes an angle. */
+void orc_qft_basis_amplitude(int n, uint64_t x, uint64_t i, double out[2])
+{
+    uint64_t y = 0;
+    for (int b = 0; b < n; ++b)
+        y |= ((i >> b) & 1u) << (n - 1 - b);
+    unsigned __int128 prod = (unsigned __int128)x * y;
+    uint64_t mask = (n == 64) ? ~(uint64_t)0 : (((uint64_t)1 << n) - 1);
+    uint64_t num = (uint64_t)prod & mask;
+    double frac = ldexp((double)num, -n);           /* exact: num < 2^53 for n <= 53 */
+    double ang = ORC_TWO_PI * frac;
+    double scale = ldexp(1.0, -n / 2) * ((n & 1) ? sqrt(0.5) : 1.0);
+    out[0] = cos(ang) * scale;
+    out[1] = sin(ang) * scale;
+}

@@ -1,0 +1,247 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests touch the GPU. Each checks the oracle against something
+other than itself: values the paper prints (golden fixtures), closed forms
+(QFT of a basis state, H on every qubit, the product-state rule), an
+independent brute-force tier (dense Kronecker operators), invariants (norm,
+mirror circuits, untouched control-0 half) and brute force on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import qcircuits as qc
+from oracle import dense
+from tests.conftest import read_golden
+
+R = math.sqrt(0.5)
+
+
+def _num(tok):
+    if tok == "r":
+        return R
+    if tok == "-r":
+        return -R
+    return float(tok)
+
+
+def _gate_matrix(name):
+    return {"X": qc.X_MATRIX, "H": qc.H_MATRIX}[name]
+
+
+# ---- golden: values printed in the paper ---------------------------------
+
+def test_pauli_x_and_hadamard_worked_values():
+    for row in read_golden("pauli_x_hadamard.txt"):
+        name, inp = row[0], int(row[1])
+        want = np.array([complex(_num(row[2]), _num(row[3])),
+                         complex(_num(row[4]), _num(row[5]))])
+        psi = oracle.basis_state(1, inp)
+        oracle.apply_1q(psi, 0, _gate_matrix(name))
+        assert np.max(np.abs(psi - want)) <= 1e-15, (name, inp)
+
+
+def test_cnot_printed_matrix_and_truth_table():
+    rows = read_golden("cnot.txt")
+    i = rows.index(["matrix"])
+    mat = np.array([[float(v) for v in r] for r in rows[i + 1:i + 5]])
+    truth = rows[rows.index(["truth"]) + 1:]
+    # control = first written qubit = qubit 1, target = qubit 0
+    for col in range(4):
+        psi = oracle.basis_state(2, col)
+        oracle.apply_ctrl(psi, 1, 0, qc.X_MATRIX)
+        assert np.array_equal(psi, mat[:, col].astype(np.complex128)), col
+    for src, dst in truth:
+        psi = oracle.basis_state(2, int(src, 2))
+        oracle.apply_ctrl(psi, 1, 0, qc.X_MATRIX)
+        assert psi[int(dst, 2)] == 1.0 and np.count_nonzero(psi) == 1
+    # the dense tier builds the same printed matrix
+    assert np.array_equal(dense.operator_ctrl(2, 1, 0, dense.matrix_of(qc.X_MATRIX)), mat)
+
+
+def _unitary_with_first_column(alpha, beta):
+    # [[alpha, -conj(beta)], [beta, conj(alpha)]] maps |0> to (alpha, beta)
+    a, b = complex(alpha), complex(beta)
+    return (a.real, a.imag, -b.real, b.imag, b.real, b.imag, a.real, -a.imag)
+
+
+def test_two_qubit_tensor_example():
+    rng = np.random.default_rng(7)
+    v = rng.normal(size=(2, 4))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    a0, b0 = complex(v[0, 0], v[0, 1]), complex(v[0, 2], v[0, 3])
+    a1, b1 = complex(v[1, 0], v[1, 1]), complex(v[1, 2], v[1, 3])
+    env = {"a0": a0, "b0": b0, "a1": a1, "b1": b1}
+    psi = oracle.basis_state(2, 0)
+    oracle.apply_1q(psi, 1, _unitary_with_first_column(a0, b0))   # paper's psi_0
+    oracle.apply_1q(psi, 0, _unitary_with_first_column(a1, b1))   # paper's psi_1
+    for idx, left, right in read_golden("tensor_2q.txt"):
+        assert abs(psi[int(idx)] - env[left] * env[right]) <= 1e-15
+
+
+def test_n3_pairing_strides_and_locality():
+    for q, stride, where in read_golden("pairs_n3.txt"):
+        q, stride = int(q), int(stride)
+        psi = np.arange(8, dtype=np.complex128)
+        oracle.apply_1q(psi, q, qc.X_MATRIX)
+        partner = psi.real.astype(int)           # X swaps each pair
+        pairs = {tuple(sorted((i, int(partner[i])))) for i in range(8)}
+        assert len(pairs) == 4
+        for lo, hi in pairs:
+            assert hi - lo == stride
+            assert ((lo < 4) == (hi < 4)) == (where == "local")
+
+
+def test_qft_two_qubit_hand_values():
+    for row in read_golden("qft_n2.txt"):
+        x = int(row[0])
+        want = np.array([complex(float(row[1 + 2 * k]), float(row[2 + 2 * k]))
+                         for k in range(4)]) / 2
+        psi = oracle.simulate(2, qc.qft_circuit(2), x)
+        assert np.max(np.abs(psi - want)) <= 1e-15, x
+        cf = oracle.qft_basis_amplitudes(2, x, range(4))
+        assert np.max(np.abs(cf - want)) <= 1e-15, x
+
+
+# ---- closed forms ---------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 11, 13])
+def test_qft_stride_tier_matches_closed_form(n):
+    for x in {0, 1, (1 << n) - 1, qc.random_basis_index(n, 100 + n)}:
+        psi = oracle.simulate(n, qc.qft_circuit(n), x)
+        cf = oracle.qft_basis_amplitudes(n, x, range(1 << n))
+        assert np.max(np.abs(psi - cf)) <= 1e-13, (n, x)
+
+
+@pytest.mark.parametrize("n", [1, 4, 10, 18])
+def test_hadamard_on_every_qubit_is_uniform(n):
+    g = np.concatenate([qc.gate_u(q, qc.H_MATRIX) for q in range(n)])
+    psi = oracle.simulate(n, g)
+    assert np.max(np.abs(psi - oracle.uniform_amplitude(n))) <= 1e-15
+
+
+def test_product_state_rule():
+    n = 9
+    su2 = qc.haar_su2(5, 40)
+    rng = np.random.default_rng(3)
+    g = np.concatenate([qc.gate_u(int(t), su2[i]) for i, t in
+                        enumerate(rng.integers(0, n, size=40))])
+    x = 0b101100101
+    psi = oracle.simulate(n, g, x)
+    vec = oracle.qubit_vectors(n, g, x)
+    want = np.array([oracle.product_state_amplitude(vec, i) for i in range(1 << n)])
+    # the Kronecker product of the per-qubit vectors, most significant first
+    kron = np.ones(1, dtype=np.complex128)
+    for q in range(n - 1, -1, -1):
+        kron = np.kron(kron, vec[q])
+    assert np.max(np.abs(want - kron)) <= 1e-15
+    assert np.max(np.abs(psi - want)) <= 1e-14
+
+
+# ---- the brute-force tier -------------------------------------------------
+
+def _mixed_circuit(n, count, seed):
+    rng = np.random.default_rng(seed)
+    su2 = qc.haar_su2(seed, count)
+    out = []
+    for i in range(count):
+        kind = int(rng.integers(0, 3)) if n > 1 else 0
+        t = int(rng.integers(0, n))
+        if kind == 0:
+            out.append(qc.gate_u(t, su2[i]))
+            continue
+        c = int(rng.integers(0, n - 1))
+        c = c + 1 if c >= t else c
+        if kind == 1:
+            out.append(qc.gate_cu(c, t, su2[i]))
+        else:
+            out.append(qc.gate_cphase(c, t, float(rng.uniform(-7, 7))))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_stride_tier_matches_dense_tier(n):
+    for seed in range(3):
+        g = _mixed_circuit(n, 30, seed + 10 * n)
+        x = seed % (1 << n)
+        psi = oracle.simulate(n, g, x)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[x] = 1
+        ref = dense.run_circuit(n, g, psi0)
+        assert np.max(np.abs(psi - ref)) <= 1e-13, (n, seed)
+
+
+def test_layer_and_qft_circuits_match_dense_tier():
+    n = 6
+    g = np.concatenate([qc.layer_circuit(n, 4, 9), qc.qft_circuit(n)])
+    psi = oracle.simulate(n, g)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    assert np.max(np.abs(psi - dense.run_circuit(n, g, psi0))) <= 1e-13
+
+
+def test_dense_operator_pins():
+    n = 4
+    for t in range(n):
+        xop = dense.operator_1q(n, t, dense.matrix_of(qc.X_MATRIX))
+        perm = np.zeros((16, 16))
+        for i in range(16):
+            perm[i ^ (1 << t), i] = 1
+        assert np.array_equal(xop, perm)
+    g = _mixed_circuit(n, 20, 4)
+    u = dense.circuit_unitary(n, g)
+    assert np.max(np.abs(u @ u.conj().T - np.eye(16))) <= 1e-13
+
+
+# ---- invariants -----------------------------------------------------------
+
+def test_norm_kept_and_mirror_returns_to_start():
+    n = 12
+    g = qc.layer_circuit(n, 10, 21)
+    psi = oracle.simulate(n, g, 5)
+    assert abs(oracle.norm(psi) - 1.0) <= 1e-13
+    oracle.run_circuit(psi, qc.inverse_circuit(g))
+    want = oracle.basis_state(n, 5)
+    assert np.max(np.abs(psi - want)) <= 1e-12
+
+
+def test_norm_and_probs_against_exact_sums():
+    rng = np.random.default_rng(0)
+    psi = (rng.normal(size=1 << 10) + 1j * rng.normal(size=1 << 10)).astype(np.complex128)
+    p = oracle.probs(psi)
+    assert np.array_equal(p, psi.real ** 2 + psi.imag ** 2)
+    assert abs(oracle.norm(psi) - math.fsum(p)) <= 1e-12 * math.fsum(p)
+    sub = oracle.probs(psi, 37, 101)
+    assert np.array_equal(sub, p[37:138])
+    assert oracle.probs(oracle.basis_state(5, 19))[19] == 1.0
+
+
+def test_controlled_gate_leaves_control_zero_half_untouched():
+    n, c, t = 7, 4, 1
+    rng = np.random.default_rng(1)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    before = psi.copy()
+    oracle.apply_ctrl(psi, c, t, qc.haar_su2(3, 1)[0])
+    idx = np.arange(1 << n)
+    untouched = (idx >> c) & 1 == 0
+    assert np.array_equal(psi[untouched], before[untouched])
+    assert not np.array_equal(psi[~untouched], before[~untouched])
+
+
+def test_cphase_is_symmetric_in_control_and_target():
+    n = 6
+    rng = np.random.default_rng(2)
+    a = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    b = a.copy()
+    oracle.apply_cphase(a, 1, 4, 0.7)
+    oracle.apply_cphase(b, 4, 1, 0.7)
+    assert np.array_equal(a, b)
+
+
+def test_malformed_gates_rejected():
+    psi = oracle.basis_state(3)
+    for bad in (qc.gate_u(3, qc.X_MATRIX), qc.gate_cnot(1, 1), qc.gate_cnot(-1, 0)):
+        with pytest.raises(ValueError):
+            oracle.run_circuit(psi, bad)
