@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the state-vector hot path at 30 qubits on one GPU.
+
+One step runs the whole hot path once over the 30-qubit workload:
+  reset to a seeded basis state |x>, QFT (465 gates: H and controlled-phase),
+  reset to |0...0>, 20 random layers (600 Haar SU(2) + 290 CNOT),
+  the FP64 norm, and the probabilities of the first 2^20 amplitudes.
+The state lives in HBM the whole time (complex128: 16 GiB; complex64: 8 GiB).
+`value` is gates per second over the timed steps in complex128 (the paper's
+precision); the complex64 run of the same steps is reported beside it.
+
+Printed: ONE JSON line on stdout. Diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+WORKLOAD_N = 30
+PROBS_COUNT = 1 << 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
+    ap.add_argument("--mode", choices=["fused", "pergate"], default="pergate",
+                    help="fused: SV_FUSE tile passes; pergate: one launch per gate")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU time budget of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c64", action="store_true")
+    return ap.parse_args()
+
+
+def workload(n):
+    import qcircuits as qc
+    x = qc.random_basis_index(n, 2024)
+    return x, qc.qft_circuit(n), qc.layer_circuit(n, 20, 1)
+
+
+def run_dtype(sv, torch, dtype, n, steps, warmup, flags):
+    """Times `steps` steps; returns a result dict with per-class event timings."""
+    x, qft, layers = workload(n)
+    gates_per_step = len(qft) + len(layers)
+    st = sv.StateVector(n, dtype)
+    probs = torch.empty(PROBS_COUNT, dtype=torch.float64, device="cuda")
+    norm_out = torch.empty(1, dtype=torch.float64, device="cuda")
+    h = st.handle
+
+    def step():
+        sv.sv_reset(h, x)
+        sv.sv_run_circuit(h, qft, flags)
+        sv.sv_reset(h, 0)
+        sv.sv_run_circuit(h, layers, flags)
+        sv.sv_norm_device(h, norm_out.data_ptr())
+        sv.sv_probs_device(h, 0, min(PROBS_COUNT, 1 << n), probs.data_ptr())
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.sv_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sv.sv_profile(h, False)
+    prof = sv.sv_profile_read(h)
+    norm = float(norm_out.item())
+    st.close()
+    del probs, norm_out
+    torch.cuda.empty_cache()
+    elapsed = t1 - t0
+    alg_bytes = sum(v["bytes"] for v in prof.values())
+    return {
+        "elapsed_s": elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "gates_per_s": gates_per_step * steps / elapsed,
+        "gates_per_step": gates_per_step,
+        "norm": norm,
+        "profile": prof,
+        "effective_hbm_frac": alg_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
+    }
+
+
+def roofline(prof):
+    """Roofline line of the kernel class with the most device time."""
+    cls, d = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = d["total_ms"] / d["launches"]
+    per_launch = d["bytes"] / d["launches"]
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"kernel": cls, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "launches": d["launches"], "avg_ms": round(avg_ms, 4),
+            "bytes_per_launch": per_launch}
+
+
+def cpu_baseline(n, budget_s):
+    """The oracle stepping the same 30-qubit layered circuit, gate by gate, on one
+    host thread, until `budget_s` seconds have been spent (at least 2 gates)."""
+    import oracle
+    _, _, layers = workload(n)
+    psi = oracle.basis_state(n, 0)
+    done, t0 = 0, time.perf_counter()
+    while done < len(layers):
+        oracle.run_circuit(psi, layers[done:done + 1])
+        done += 1
+        if done >= 2 and time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    del psi
+    return {"value": round(done / el, 5), "unit": "gates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} gates of the {n}-qubit depth-20 layered circuit "
+                      f"(complex128, from |0>), {el:.1f} s on one host thread"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures one GPU only: this build has no multi-GPU path "
+            f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).")
+        sys.exit(2)
+    import torch
+    import paper_1801_01037_amd as sv
+    if not os.path.exists(sv.LIB_PATH):
+        from paper_1801_01037_amd import build
+        build.build()
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    flags = sv.SV_FUSE if args.mode == "fused" else 0
+    n = args.qubits
+    log(f"[bench] c128 n={n} mode={args.mode} steps={args.steps} warmup={args.warmup}")
+    r128 = run_dtype(sv, torch, sv.SV_C128, n, args.steps, args.warmup, flags)
+    log(f"[bench] c128 {r128['gates_per_s']:.1f} gates/s, {r128['ms_per_step']:.1f} ms/step")
+    out_c64 = None
+    if not args.no_c64:
+        r64 = run_dtype(sv, torch, sv.SV_C64, n, args.steps, args.warmup, flags)
+        log(f"[bench] c64 {r64['gates_per_s']:.1f} gates/s, {r64['ms_per_step']:.1f} ms/step")
+        out_c64 = {"value": round(r64["gates_per_s"], 3), "unit": "gates/s", "dtype": "f32",
+                   "ms_per_step": round(r64["ms_per_step"], 3),
+                   "effective_hbm_frac": round(r64["effective_hbm_frac"], 4),
+                   "speedup_vs_c128": round(r64["gates_per_s"] / r128["gates_per_s"], 3),
+                   "roofline": roofline(r64["profile"]), "norm": r64["norm"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
+        cpu = cpu_baseline(n, args.cpu_seconds)
+    line = {
+        "metric": "30q gates/s and % HBM peak, c64 vs c128; batched p50/p99 circuit latency",
+        "value": round(r128["gates_per_s"], 3),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r128["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{n}-qubit QFT of a seeded basis state + {n}-qubit depth-20 "
+                               "Haar-SU(2)/CNOT layers, complex128, then norm and 2^20 probs",
+                   "n_qubits": n, "gates_per_step": r128["gates_per_step"],
+                   "mode": args.mode, "parallelism": "single GPU"},
+        "effective_hbm_frac": round(r128["effective_hbm_frac"], 4),
+        "roofline": roofline(r128["profile"]),
+        "cpu_baseline": cpu,
+        "c64": out_c64,
+        "kernels_c128": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
+                             "GBps": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)}
+                         for k, v in r128["profile"].items()},
+        "norm_c128": r128["norm"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

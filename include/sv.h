@@ -1,0 +1,192 @@
+/*
+ * sv.h -- C ABI of the MI355X state-vector simulator (libsv.so).
+ *
+ * The problem it solves is the one stated in R. LaRose, "Distributed Memory
+ * Techniques for Classical Simulation of Quantum Circuits" (arXiv:1801.01037),
+ * section State Vector Partitioning:
+ *   - an n-qubit register is the vector of 2^n complex amplitudes
+ *     alpha_{b_{n-1}...b_0}, indexed in binary (the three-qubit
+ *     binary-index equation);
+ *   - a one-qubit gate Q = [[q11, q12], [q21, q22]] on qubit i replaces every
+ *     pair of amplitudes whose indices differ only in bit i by
+ *     (q11 a + q12 b, q21 a + q22 b) (the stride update equation);
+ *   - a gate with control c and target t does the same only where bit c of
+ *     the index is one (caption of Algorithm 1);
+ *   - a circuit is a sequence of such gates (Quantum Circuits).
+ *
+ * Conventions shared by every entry point:
+ *   - Qubit q is bit q of the amplitude index (stride 2^q). Valid n: 1..34.
+ *   - Amplitudes are stored contiguously and interleaved (re, im): float2 for
+ *     SV_C64 (8 bytes each), double2 for SV_C128 (16 bytes each); the layout of
+ *     torch.complex64 / torch.complex128.
+ *   - Gate matrices are always passed as 8 doubles: q11, q12, q21, q22 as
+ *     (re, im) pairs, row major. They are read during the call only. For
+ *     SV_C64 they are rounded once to float. Unitarity is assumed, not checked.
+ *   - Asynchrony: calls that change the state enqueue work on the handle's
+ *     HIP stream and return. Device faults surface as SV_EDEVICE from the next
+ *     call that synchronises (sv_probs, sv_norm, sv_copy_out, sv_synchronize).
+ *   - Errors: every call returns an sv_status; SV_OK is 0. The message of the
+ *     last failure on the calling thread is in sv_last_error(). No C++
+ *     exception crosses this boundary. A failed call leaves the state as it
+ *     was unless the status is SV_EDEVICE.
+ *   - Threads: one handle must not be used from two threads at once; distinct
+ *     handles may be used concurrently.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_state_s *sv_state;   /* opaque handle */
+
+typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = -1,        /* bad argument: null pointer, qubit out of range, ... */
+    SV_ENOMEM = -2,        /* device or host allocation failed */
+    SV_EDEVICE = -3,       /* a HIP runtime call or a kernel failed */
+    SV_EUNSUPPORTED = -4   /* valid request this build does not serve */
+} sv_status;
+
+/* Gate kinds of sv_gate.kind. */
+enum {
+    SV_G_U = 0,       /* 2x2 matrix m on `target`; `control` must be -1            */
+    SV_G_CU = 1,      /* 2x2 matrix m on `target` where bit `control` is 1 (CNOT:  */
+                      /* m = X)                                                    */
+    SV_G_CPHASE = 2   /* diag(1, e^{i theta}) on `target` where bit `control` is 1; */
+                      /* theta = m[0] in radians (controlled-phase R_k has         */
+                      /* theta = 2 pi / 2^k)                                       */
+};
+
+/* One gate of a circuit: 80 bytes, the same record the seeded generators
+ * write. `flags` is reserved and must be 0. */
+typedef struct {
+    int32_t kind;
+    int32_t control;    /* -1 when the gate has no control */
+    int32_t target;
+    int32_t flags;
+    double m[8];        /* q11, q12, q21, q22 as (re, im); SV_G_CPHASE: m[0] = theta */
+} sv_gate;
+
+/* sv_run_circuit flags. With no flag every gate is its own kernel launch
+ * (one pass over the state per gate). */
+#define SV_FUSE        1u  /* group gates into LDS-tile passes: each pass reads and */
+                           /* writes the state once and applies every gate whose    */
+                           /* target lies in the pass's tile qubits                 */
+#define SV_FUSE_DENSE  2u  /* group gates into dense 2^k x 2^k blocks on k <= 5      */
+                           /* qubits, multiplied on the matrix cores (MFMA)          */
+#define SV_GRAPH       4u  /* capture the launches of this call in a HIP graph and   */
+                           /* replay it; the graph is cached on the handle keyed by  */
+                           /* the gate list, so a repeated identical call only       */
+                           /* replays                                                */
+
+/* ABI version; bumped when a signature or struct changes. */
+int sv_version(void);
+
+/* Thread-local message of the last failed call ("" when none). The pointer is
+ * valid until the next call on the same thread. */
+const char *sv_last_error(void);
+
+/* Allocates a 2^n_qubits state in device memory on the current HIP device,
+ * owned by the handle, and sets it to |0...0> (the register's starting state).
+ * hip_stream: a hipStream_t, or NULL for the null stream. The handle owns the
+ * memory until sv_destroy. SV_ENOMEM if hipMalloc fails. */
+sv_status sv_create(int n_qubits, sv_dtype dtype, void *hip_stream, sv_state *out);
+
+/* Wraps caller-owned device memory of 2^n_qubits amplitudes (e.g. a torch
+ * tensor's data_ptr()). The contents are left as they are. The caller keeps
+ * the memory alive until sv_destroy, which does not free it. dev_ptr must be
+ * 16-byte aligned. */
+sv_status sv_wrap(void *dev_ptr, int n_qubits, sv_dtype dtype, void *hip_stream,
+                  sv_state *out);
+
+/* Releases the handle, its scratch buffers and (for sv_create) its state.
+ * Waits for the handle's stream first. NULL is accepted. */
+sv_status sv_destroy(sv_state s);
+
+/* Changes the stream later calls enqueue on. The caller orders any work
+ * already queued on the old stream. */
+sv_status sv_set_stream(sv_state s, void *hip_stream);
+
+/* Device pointer, qubit count and dtype of a handle (any out may be NULL). */
+sv_status sv_info(sv_state s, void **dev_ptr, int *n_qubits, sv_dtype *dtype);
+
+/* Sets the state to the basis state |basis_index> (basis_index < 2^n). */
+sv_status sv_reset(sv_state s, uint64_t basis_index);
+
+/* Applies the 2x2 matrix m to qubit `target`: the stride update of section
+ * State Vector Partitioning, one pass over the state. */
+sv_status sv_apply_1q(sv_state s, int target, const double m[8]);
+
+/* Applies m to `target` on the amplitudes whose index has bit `control` set
+ * (caption of Algorithm 1). control != target. CNOT is m = X; a controlled
+ * phase is m = diag(1, e^{i theta}). */
+sv_status sv_apply_ctrl(sv_state s, int control, int target, const double m[8]);
+
+/* Controlled phase diag(1, e^{i theta}) on (control, target); symmetric in the
+ * two qubits. The phase e^{i theta} is formed in FP64 for both dtypes. */
+sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
+
+/* Applies n_gates gates in order (the circuit of section Quantum Circuits).
+ * The gate array is read during the call only. flags: 0, SV_FUSE,
+ * SV_FUSE_DENSE, optionally | SV_GRAPH. Fusion reorders only gates that act on
+ * disjoint qubits, so the result equals the in-order product up to rounding.
+ * All gates are validated before any work is queued. */
+sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags);
+
+/* p_i = |alpha_i|^2 for i in [first, first + count), written to host memory
+ * out_host (count doubles). Synchronous: waits for the stream. The squares are
+ * formed in FP64 for both dtypes. */
+sv_status sv_probs(sv_state s, uint64_t first, uint64_t count, double *out_host);
+
+/* As sv_probs, but writes to device memory out_dev (count doubles, 8-byte
+ * aligned) and returns without waiting. */
+sv_status sv_probs_device(sv_state s, uint64_t first, uint64_t count, double *out_dev);
+
+/* sum_i |alpha_i|^2 accumulated in FP64 by a fixed two-level tree (the same
+ * result bit for bit on every call for the same state). Synchronous. */
+sv_status sv_norm(sv_state s, double *out);
+
+/* As sv_norm, but writes the double to device memory and returns without
+ * waiting. */
+sv_status sv_norm_device(sv_state s, double *out_dev);
+
+/* Copies the whole state (2^n amplitudes in the layout above) to / from host
+ * memory. Synchronous. */
+sv_status sv_copy_out(sv_state s, void *host_dst);
+sv_status sv_copy_in(sv_state s, const void *host_src);
+
+/* Waits for the handle's stream; SV_EDEVICE if queued work failed. */
+sv_status sv_synchronize(sv_state s);
+
+/* Per-kernel-class timing of the launches this handle queues, measured with
+ * HIP events recorded on the handle's stream around each launch. */
+typedef struct {
+    char name[16];       /* kernel class: "pair", "pair_ctrl", "swap", "diag", ... */
+    uint64_t launches;   /* launches timed */
+    double total_ms;     /* summed event-to-event time of those launches */
+    double bytes;        /* algorithmic bytes they had to read and write */
+    double flops;        /* algorithmic floating-point operations */
+} sv_prof_entry;
+
+/* enable != 0: waits for the stream, clears earlier records and starts timing
+ * every later launch of this handle; enable == 0 stops timing (records are
+ * kept for sv_profile_read). */
+sv_status sv_profile(sv_state s, int enable);
+
+/* Waits for the stream and writes up to max_entries classes that have at
+ * least one timed launch to out; *n_entries receives the number of such
+ * classes (which may exceed max_entries). */
+sv_status sv_profile_read(sv_state s, sv_prof_entry *out, int max_entries, int *n_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

@@ -1,0 +1,294 @@
+"""MI355X state-vector simulator: a thin ctypes binding of libsv.so.
+
+Every function here has the name and meaning of the C entry point declared in
+include/sv.h and only marshals arguments; all state work runs in the HIP
+kernels of libsv.so. There is no CPU fallback: if the library is missing the
+import of any entry point raises.
+
+`StateVector` is a convenience wrapper that takes its device memory and stream
+from PyTorch (torch.complex64 / torch.complex128 tensors on the GPU) and
+passes them to sv_wrap.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SVError", "lib",
+    "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
+    "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_cphase",
+    "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
+    "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
+    "StateVector", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsv.so")
+
+SV_C64 = 1
+SV_C128 = 2
+SV_FUSE = 1
+SV_FUSE_DENSE = 2
+SV_GRAPH = 4
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
+_STATUS_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM",
+                 SV_EDEVICE: "SV_EDEVICE", SV_EUNSUPPORTED: "SV_EUNSUPPORTED"}
+
+GATE_DTYPE = np.dtype([
+    ("kind", "<i4"), ("control", "<i4"), ("target", "<i4"), ("flags", "<i4"),
+    ("m", "<f8", (8,)),
+])
+
+
+class SVError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 16), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+_lib = None
+_vp, _u64, _int, _u32, _sz = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                              ctypes.c_uint32, ctypes.c_size_t)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "sv_version": ([], ctypes.c_int),
+    "sv_last_error": ([], ctypes.c_char_p),
+    "sv_create": ([_int, _int, _vp, ctypes.POINTER(_vp)], _int),
+    "sv_wrap": ([_vp, _int, _int, _vp, ctypes.POINTER(_vp)], _int),
+    "sv_destroy": ([_vp], _int),
+    "sv_set_stream": ([_vp, _vp], _int),
+    "sv_info": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
+    "sv_reset": ([_vp, _u64], _int),
+    "sv_apply_1q": ([_vp, _int, _dp], _int),
+    "sv_apply_ctrl": ([_vp, _int, _int, _dp], _int),
+    "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
+    "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
+    "sv_probs": ([_vp, _u64, _u64, _dp], _int),
+    "sv_probs_device": ([_vp, _u64, _u64, _vp], _int),
+    "sv_norm": ([_vp, _dp], _int),
+    "sv_norm_device": ([_vp, _vp], _int),
+    "sv_copy_out": ([_vp, _vp], _int),
+    "sv_copy_in": ([_vp, _vp], _int),
+    "sv_synchronize": ([_vp], _int),
+    "sv_profile": ([_vp, _int], _int),
+    "sv_profile_read": ([_vp, ctypes.POINTER(_ProfEntry), _int, ctypes.POINTER(_int)], _int),
+}
+
+
+def lib():
+    """The loaded libsv.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_1801_01037_amd/build.py` (there is no fallback)")
+        # PyTorch ships its own HIP runtime under a file name the system one
+        # does not satisfy. Loading torch first makes libsv's libamdhip64.so.7
+        # resolve to that already-loaded runtime, so the process holds one HIP
+        # runtime whichever of the two is used first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != SV_OK:
+        raise SVError(status, sv_last_error())
+
+
+def _mat(m) -> ctypes.Array:
+    a = np.ascontiguousarray(m, dtype=np.float64)
+    if a.shape != (8,):
+        raise ValueError("a gate matrix is 8 doubles: q11, q12, q21, q22 as (re, im)")
+    return (ctypes.c_double * 8)(*a.tolist())
+
+
+def sv_version() -> int:
+    return lib().sv_version()
+
+
+def sv_last_error() -> str:
+    return lib().sv_last_error().decode()
+
+
+def sv_create(n_qubits: int, dtype: int, stream: int | None = None) -> int:
+    h = _vp()
+    _check(lib().sv_create(n_qubits, dtype, stream, ctypes.byref(h)))
+    return h.value
+
+
+def sv_wrap(dev_ptr: int, n_qubits: int, dtype: int, stream: int | None = None) -> int:
+    h = _vp()
+    _check(lib().sv_wrap(dev_ptr, n_qubits, dtype, stream, ctypes.byref(h)))
+    return h.value
+
+
+def sv_destroy(h: int) -> None:
+    _check(lib().sv_destroy(h))
+
+
+def sv_set_stream(h: int, stream: int | None) -> None:
+    _check(lib().sv_set_stream(h, stream))
+
+
+def sv_info(h: int):
+    p, n, dt = _vp(), _int(), _int()
+    _check(lib().sv_info(h, ctypes.byref(p), ctypes.byref(n), ctypes.byref(dt)))
+    return p.value, n.value, dt.value
+
+
+def sv_reset(h: int, basis_index: int = 0) -> None:
+    _check(lib().sv_reset(h, basis_index))
+
+
+def sv_apply_1q(h: int, target: int, m) -> None:
+    _check(lib().sv_apply_1q(h, target, _mat(m)))
+
+
+def sv_apply_ctrl(h: int, control: int, target: int, m) -> None:
+    _check(lib().sv_apply_ctrl(h, control, target, _mat(m)))
+
+
+def sv_apply_cphase(h: int, control: int, target: int, theta: float) -> None:
+    _check(lib().sv_apply_cphase(h, control, target, float(theta)))
+
+
+def sv_run_circuit(h: int, gates: np.ndarray, flags: int = 0) -> None:
+    g = np.ascontiguousarray(gates)
+    if g.dtype != GATE_DTYPE:
+        g = g.astype(GATE_DTYPE)
+    _check(lib().sv_run_circuit(h, g.ctypes.data if len(g) else None, len(g), flags))
+
+
+def sv_probs(h: int, first: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.float64)
+    _check(lib().sv_probs(h, first, count, out.ctypes.data_as(_dp)))
+    return out
+
+
+def sv_probs_device(h: int, first: int, count: int, out_dev: int) -> None:
+    _check(lib().sv_probs_device(h, first, count, out_dev))
+
+
+def sv_norm(h: int) -> float:
+    v = ctypes.c_double()
+    _check(lib().sv_norm(h, ctypes.byref(v)))
+    return v.value
+
+
+def sv_norm_device(h: int, out_dev: int) -> None:
+    _check(lib().sv_norm_device(h, out_dev))
+
+
+def sv_copy_out(h: int) -> np.ndarray:
+    _, n, dt = sv_info(h)
+    out = np.empty(1 << n, dtype=np.complex64 if dt == SV_C64 else np.complex128)
+    _check(lib().sv_copy_out(h, out.ctypes.data))
+    return out
+
+
+def sv_copy_in(h: int, host: np.ndarray) -> None:
+    _, n, dt = sv_info(h)
+    want = np.complex64 if dt == SV_C64 else np.complex128
+    a = np.ascontiguousarray(host, dtype=want)
+    if a.size != 1 << n:
+        raise ValueError(f"expected {1 << n} amplitudes, got {a.size}")
+    _check(lib().sv_copy_in(h, a.ctypes.data))
+
+
+def sv_synchronize(h: int) -> None:
+    _check(lib().sv_synchronize(h))
+
+
+def sv_profile(h: int, enable: bool) -> None:
+    _check(lib().sv_profile(h, 1 if enable else 0))
+
+
+def sv_profile_read(h: int) -> dict:
+    """{kernel class: {launches, total_ms, bytes, flops}} of the timed launches."""
+    buf = (_ProfEntry * 16)()
+    cnt = _int()
+    _check(lib().sv_profile_read(h, buf, 16, ctypes.byref(cnt)))
+    return {e.name.decode(): {"launches": int(e.launches), "total_ms": e.total_ms,
+                              "bytes": e.bytes, "flops": e.flops}
+            for e in buf[:min(cnt.value, 16)]}
+
+
+class StateVector:
+    """A state whose device memory is a torch tensor, driven through libsv."""
+
+    def __init__(self, n_qubits: int, dtype: int = SV_C128, device: int = 0,
+                 stream=None, basis_index: int = 0):
+        import torch
+        tdt = torch.complex64 if dtype == SV_C64 else torch.complex128
+        self.n, self.dtype = n_qubits, dtype
+        self.tensor = torch.empty(1 << n_qubits, dtype=tdt, device=f"cuda:{device}")
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        self.handle = sv_wrap(self.tensor.data_ptr(), n_qubits, dtype, s.cuda_stream)
+        sv_reset(self.handle, basis_index)
+
+    def reset(self, basis_index: int = 0):
+        sv_reset(self.handle, basis_index)
+
+    def apply_1q(self, target, m):
+        sv_apply_1q(self.handle, target, m)
+
+    def apply_ctrl(self, control, target, m):
+        sv_apply_ctrl(self.handle, control, target, m)
+
+    def apply_cphase(self, control, target, theta):
+        sv_apply_cphase(self.handle, control, target, theta)
+
+    def run(self, gates, flags: int = 0):
+        sv_run_circuit(self.handle, gates, flags)
+
+    def probs(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - first
+        return sv_probs(self.handle, first, count)
+
+    def norm(self) -> float:
+        return sv_norm(self.handle)
+
+    def numpy(self) -> np.ndarray:
+        return sv_copy_out(self.handle)
+
+    def synchronize(self):
+        sv_synchronize(self.handle)
+
+    def close(self):
+        if self.handle:
+            sv_destroy(self.handle)
+            self.handle = None
+            self.tensor = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

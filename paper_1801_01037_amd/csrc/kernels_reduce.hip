@@ -1,0 +1,112 @@
+// Norm and probability reductions. Squares and sums are formed in FP64 for
+// both storage precisions (the normalisation condition sum |alpha_i|^2 = 1 of
+// Quantum Information Processing).
+//
+// The norm is a fixed two-level tree: kNormBlocks blocks each sum a fixed,
+// strided subset of the 16-byte chunks (thread-sequential, then a wave
+// shuffle tree, then across waves), and one block sums the partials in a
+// fixed order. No floating-point atomics, so a state gives the same bits on
+// every call.
+#include <type_traits>
+
+#include "sv_internal.h"
+
+namespace svk {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over a block of `kThreads` threads; result valid in thread 0.
+template <int kThreads>
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double part[kThreads / 64];
+    v = wave_sum(v);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) s += part[w];
+    return s;
+}
+
+template <bool C64>
+__global__ __launch_bounds__(kBlock) void k_norm_partial(const void *psi, uint64_t chunks,
+                                                         double *partials)
+{
+    using V = std::conditional_t<C64, float4, double2>;
+    const V *p = static_cast<const V *>(psi);
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    double acc = 0.0;
+    for (uint64_t c = uint64_t(blockIdx.x) * kBlock + threadIdx.x; c < chunks; c += stride) {
+        const V v = p[c];
+        if constexpr (C64) {
+            const double a = v.x, b = v.y, d = v.z, e = v.w;
+            acc += (a * a + b * b) + (d * d + e * e);
+        } else {
+            acc += v.x * v.x + v.y * v.y;
+        }
+    }
+    const double s = block_sum<kBlock>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kNormBlocks) void k_norm_final(const double *partials, double *out)
+{
+    const double s = block_sum<kNormBlocks>(partials[threadIdx.x]);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <bool C64>
+__global__ __launch_bounds__(kBlock) void k_probs(const void *psi, uint64_t first,
+                                                  uint64_t count, double *out)
+{
+    using A = std::conditional_t<C64, float2, double2>;
+    const A *p = static_cast<const A *>(psi) + first;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += stride) {
+        const A v = p[i];
+        const double re = v.x, im = v.y;
+        out[i] = re * re + im * im;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_norm(const void *psi, int n, sv_dtype dt, double *partials, double *out_dev,
+                       hipStream_t st)
+{
+    const uint64_t chunks = (uint64_t(1) << n) >> chunk_log2(dt);
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_norm_partial<true>, dim3(kNormBlocks), dim3(kBlock), 0, st, psi,
+                           chunks, partials);
+    else
+        hipLaunchKernelGGL(k_norm_partial<false>, dim3(kNormBlocks), dim3(kBlock), 0, st, psi,
+                           chunks, partials);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormBlocks), 0, st, partials, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_probs(const void *psi, sv_dtype dt, uint64_t first, uint64_t count,
+                        double *out_dev, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    const unsigned grid = unsigned(std::min<uint64_t>((count + kBlock - 1) / kBlock, 16384));
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_probs<true>, dim3(grid), dim3(kBlock), 0, st, psi, first, count,
+                           out_dev);
+    else
+        hipLaunchKernelGGL(k_probs<false>, dim3(grid), dim3(kBlock), 0, st, psi, first, count,
+                           out_dev);
+    return hipGetLastError();
+}
+
+}  // namespace svk

@@ -1,0 +1,429 @@
+// The C ABI declared in include/sv.h: argument checks, handle management and
+// dispatch of each request to the kernels. No exception leaves this file.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "sv_internal.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sv_status fail(sv_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+sv_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SV_HIP(call, what)                            \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Makes the handle's device current for the scope of one call.
+class DeviceScope {
+public:
+    explicit DeviceScope(int dev)
+    {
+        if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev && hipSetDevice(dev) == hipSuccess)
+            switched_ = true;
+    }
+    ~DeviceScope()
+    {
+        if (switched_) (void)hipSetDevice(prev_);
+    }
+
+private:
+    int prev_ = 0;
+    bool switched_ = false;
+};
+
+bool valid_dtype(sv_dtype dt) { return dt == SV_C64 || dt == SV_C128; }
+
+uint64_t state_bytes(const sv_state_s *s) { return (uint64_t(1) << s->n) * svk::elem_bytes(s->dt); }
+
+sv_status check_handle(sv_state s)
+{
+    if (!s) return fail(SV_EINVAL, "null state handle");
+    return SV_OK;
+}
+
+sv_status make_handle(void *psi, int n, sv_dtype dt, void *stream, bool owned, sv_state *out)
+{
+    sv_state_s *s = new (std::nothrow) sv_state_s;
+    if (!s) return fail(SV_ENOMEM, "host allocation of the handle failed");
+    s->psi = psi;
+    s->n = n;
+    s->dt = dt;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->owned = owned;
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
+    hipError_t e = hipMalloc(&s->scratch, (svk::kNormBlocks + 1) * sizeof(double));
+    if (e != hipSuccess) {
+        delete s;
+        return fail(SV_ENOMEM, "hipMalloc of reduction scratch failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return SV_OK;
+}
+
+// Queues one gate as its own kernel (one pass over the touched amplitudes).
+sv_status queue_gate(sv_state s, const sv_gate &g)
+{
+    svk::Mat2 m;
+    std::memcpy(m.q, g.m, sizeof m.q);
+    const double N = std::ldexp(1.0, s->n), sb = svk::elem_bytes(s->dt);
+    const uint64_t tbit = uint64_t(1) << g.target;
+    const uint64_t both = g.kind == SV_G_U ? tbit : tbit | (uint64_t(1) << g.control);
+    const bool ctrl = g.kind != SV_G_U;
+    // Kind of kernel, and the amplitudes it must read and write.
+    enum { PAIR, SWAP, DIAG } how;
+    if (g.kind == SV_G_CPHASE) how = DIAG;
+    else if (svk::is_pauli_x(g.m)) how = SWAP;
+    else if (svk::is_phase_diag(g.m)) how = DIAG;
+    else how = PAIR;
+    const double touched = how == DIAG ? (ctrl ? N / 4 : N / 2) : (ctrl ? N / 2 : N);
+    int cls;
+    double flops;
+    if (how == PAIR) { cls = ctrl ? svk::KC_PAIR_CTRL : svk::KC_PAIR; flops = 14 * touched; }
+    else if (how == SWAP) { cls = svk::KC_SWAP; flops = 0; }
+    else { cls = svk::KC_DIAG; flops = 6 * touched; }
+
+    const int tok = svk::prof_begin(s);
+    hipError_t e;
+    if (how == PAIR || how == SWAP) {
+        e = svk::launch_pair(s->psi, s->n, s->dt, g.target, ctrl ? g.control : -1, m,
+                             how == SWAP, s->stream);
+    } else {
+        const double theta = g.kind == SV_G_CPHASE ? g.m[0] : std::atan2(g.m[7], g.m[6]);
+        svk::DiagTerm t{both, both, svk::angle_to_turn(theta)};
+        e = svk::launch_diag(s->psi, s->n, s->dt, &t, 1, s->stream);
+    }
+    svk::prof_end(s, tok, cls, 2 * touched * sb, flops);
+    if (e != hipSuccess) return hip_fail(e, "gate kernel launch");
+    return SV_OK;
+}
+
+sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
+{
+    if (g.flags != 0) return fail(SV_EINVAL, "gate %zu: flags must be 0", idx);
+    if (g.target < 0 || g.target >= s->n)
+        return fail(SV_EINVAL, "gate %zu: target %d out of range [0, %d)", idx, g.target, s->n);
+    switch (g.kind) {
+    case SV_G_U:
+        if (g.control != -1) return fail(SV_EINVAL, "gate %zu: SV_G_U takes control -1", idx);
+        break;
+    case SV_G_CU:
+    case SV_G_CPHASE:
+        if (g.control < 0 || g.control >= s->n)
+            return fail(SV_EINVAL, "gate %zu: control %d out of range [0, %d)", idx, g.control, s->n);
+        if (g.control == g.target)
+            return fail(SV_EINVAL, "gate %zu: control equals target (%d)", idx, g.target);
+        break;
+    default:
+        return fail(SV_EINVAL, "gate %zu: unknown kind %d", idx, g.kind);
+    }
+    const int nm = g.kind == SV_G_CPHASE ? 1 : 8;
+    for (int k = 0; k < nm; ++k)
+        if (!std::isfinite(g.m[k])) return fail(SV_EINVAL, "gate %zu: non-finite matrix entry", idx);
+    return SV_OK;
+}
+
+}  // namespace
+
+namespace svk {
+
+uint64_t angle_to_turn(double theta)
+{
+    // theta / (2 pi) as a fraction of a turn in [0, 1), scaled by 2^64. For
+    // theta = (2 pi) / 2^k the quotient is exactly 2^-k.
+    const double two_pi = 6.283185307179586476925286766559;
+    double f = theta / two_pi;
+    f -= std::floor(f);
+    double scaled = std::ldexp(f, 64);
+    if (!(scaled < 18446744073709551616.0)) return 0;
+    return uint64_t(scaled);
+}
+
+bool is_pauli_x(const double m[8])
+{
+    return m[0] == 0 && m[1] == 0 && m[2] == 1 && m[3] == 0 && m[4] == 1 && m[5] == 0 &&
+           m[6] == 0 && m[7] == 0;
+}
+
+bool is_phase_diag(const double m[8])
+{
+    if (!(m[0] == 1 && m[1] == 0 && m[2] == 0 && m[3] == 0 && m[4] == 0 && m[5] == 0))
+        return false;
+    const double mod2 = m[6] * m[6] + m[7] * m[7];
+    return std::fabs(mod2 - 1.0) <= 4e-16;
+}
+
+}  // namespace svk
+
+extern "C" {
+
+int sv_version(void) { return 1; }
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+sv_status sv_create(int n_qubits, sv_dtype dtype, void *hip_stream, sv_state *out)
+{
+    if (!out) return fail(SV_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (!valid_dtype(dtype)) return fail(SV_EINVAL, "unknown dtype %d", int(dtype));
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [1, 34]", n_qubits);
+    const uint64_t bytes = (uint64_t(1) << n_qubits) * svk::elem_bytes(dtype);
+    void *psi = nullptr;
+    hipError_t e = hipMalloc(&psi, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ENOMEM, "hipMalloc of %llu bytes failed: %s", (unsigned long long)bytes,
+                    hipGetErrorString(e));
+    }
+    sv_state s = nullptr;
+    sv_status st = make_handle(psi, n_qubits, dtype, hip_stream, true, &s);
+    if (st != SV_OK) {
+        (void)hipFree(psi);
+        return st;
+    }
+    e = svk::launch_init(psi, n_qubits, dtype, 0, s->stream);
+    if (e != hipSuccess) {
+        sv_destroy(s);
+        return hip_fail(e, "init kernel launch");
+    }
+    *out = s;
+    return SV_OK;
+}
+
+sv_status sv_wrap(void *dev_ptr, int n_qubits, sv_dtype dtype, void *hip_stream, sv_state *out)
+{
+    if (!out) return fail(SV_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (!dev_ptr) return fail(SV_EINVAL, "null device pointer");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 16 != 0)
+        return fail(SV_EINVAL, "device pointer is not 16-byte aligned");
+    if (!valid_dtype(dtype)) return fail(SV_EINVAL, "unknown dtype %d", int(dtype));
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [1, 34]", n_qubits);
+    return make_handle(dev_ptr, n_qubits, dtype, hip_stream, false, out);
+}
+
+sv_status sv_destroy(sv_state s)
+{
+    if (!s) return SV_OK;
+    DeviceScope ds(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    svk::plan_release(s);
+    svk::prof_release(s);
+    if (s->scratch) (void)hipFree(s->scratch);
+    if (s->owned && s->psi) (void)hipFree(s->psi);
+    delete s;
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize in sv_destroy");
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_state s, void *hip_stream)
+{
+    if (sv_status st = check_handle(s)) return st;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return SV_OK;
+}
+
+sv_status sv_info(sv_state s, void **dev_ptr, int *n_qubits, sv_dtype *dtype)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (dev_ptr) *dev_ptr = s->psi;
+    if (n_qubits) *n_qubits = s->n;
+    if (dtype) *dtype = s->dt;
+    return SV_OK;
+}
+
+sv_status sv_reset(sv_state s, uint64_t basis_index)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (basis_index >> s->n)
+        return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)basis_index, s->n);
+    DeviceScope ds(s->device);
+    const int tok = svk::prof_begin(s);
+    hipError_t e = svk::launch_init(s->psi, s->n, s->dt, basis_index, s->stream);
+    svk::prof_end(s, tok, svk::KC_INIT, double(state_bytes(s)), 0);
+    if (e != hipSuccess) return hip_fail(e, "init kernel launch");
+    return SV_OK;
+}
+
+sv_status sv_apply_1q(sv_state s, int target, const double m[8])
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!m) return fail(SV_EINVAL, "null matrix");
+    sv_gate g{SV_G_U, -1, target, 0, {}};
+    std::memcpy(g.m, m, sizeof g.m);
+    if (sv_status st = validate_gate(s, g, 0)) return st;
+    DeviceScope ds(s->device);
+    return queue_gate(s, g);
+}
+
+sv_status sv_apply_ctrl(sv_state s, int control, int target, const double m[8])
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!m) return fail(SV_EINVAL, "null matrix");
+    sv_gate g{SV_G_CU, control, target, 0, {}};
+    std::memcpy(g.m, m, sizeof g.m);
+    if (sv_status st = validate_gate(s, g, 0)) return st;
+    DeviceScope ds(s->device);
+    return queue_gate(s, g);
+}
+
+sv_status sv_apply_cphase(sv_state s, int control, int target, double theta)
+{
+    if (sv_status st = check_handle(s)) return st;
+    sv_gate g{SV_G_CPHASE, control, target, 0, {theta}};
+    if (sv_status st = validate_gate(s, g, 0)) return st;
+    DeviceScope ds(s->device);
+    return queue_gate(s, g);
+}
+
+sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (n_gates == 0) return SV_OK;
+    if (!gates) return fail(SV_EINVAL, "null gate array");
+    if (flags & ~(SV_FUSE | SV_FUSE_DENSE | SV_GRAPH)) return fail(SV_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & SV_FUSE) && (flags & SV_FUSE_DENSE))
+        return fail(SV_EINVAL, "SV_FUSE and SV_FUSE_DENSE are exclusive");
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = validate_gate(s, gates[i], i)) return st;
+    DeviceScope ds(s->device);
+    if (flags & (SV_FUSE | SV_FUSE_DENSE | SV_GRAPH)) {
+        std::string err;
+        sv_status st = svk::plan_run(s, gates, n_gates, flags, &err);
+        if (st != SV_OK) return fail(st, "%s", err.c_str());
+        return SV_OK;
+    }
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = queue_gate(s, gates[i])) return st;
+    return SV_OK;
+}
+
+sv_status sv_probs_device(sv_state s, uint64_t first, uint64_t count, double *out_dev)
+{
+    if (sv_status st = check_handle(s)) return st;
+    const uint64_t N = uint64_t(1) << s->n;
+    if (first > N || count > N - first)
+        return fail(SV_EINVAL, "range [%llu, +%llu) exceeds 2^%d", (unsigned long long)first,
+                    (unsigned long long)count, s->n);
+    if (count == 0) return SV_OK;
+    if (!out_dev) return fail(SV_EINVAL, "null output pointer");
+    if (reinterpret_cast<uintptr_t>(out_dev) % 8 != 0)
+        return fail(SV_EINVAL, "output pointer is not 8-byte aligned");
+    DeviceScope ds(s->device);
+    const int tok = svk::prof_begin(s);
+    hipError_t e = svk::launch_probs(s->psi, s->dt, first, count, out_dev, s->stream);
+    svk::prof_end(s, tok, svk::KC_PROBS, double(count) * (svk::elem_bytes(s->dt) + 8),
+                  3.0 * double(count));
+    if (e != hipSuccess) return hip_fail(e, "probs kernel launch");
+    return SV_OK;
+}
+
+sv_status sv_probs(sv_state s, uint64_t first, uint64_t count, double *out_host)
+{
+    if (sv_status st = check_handle(s)) return st;
+    const uint64_t N = uint64_t(1) << s->n;
+    if (first > N || count > N - first)
+        return fail(SV_EINVAL, "range [%llu, +%llu) exceeds 2^%d", (unsigned long long)first,
+                    (unsigned long long)count, s->n);
+    if (count == 0) return SV_OK;
+    if (!out_host) return fail(SV_EINVAL, "null output pointer");
+    DeviceScope ds(s->device);
+    // Staged through a bounded device buffer so that a range of the largest
+    // states never needs a second state-sized allocation.
+    const uint64_t stage = std::min<uint64_t>(count, uint64_t(1) << 23);
+    double *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, stage * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ENOMEM, "hipMalloc of probs staging failed: %s", hipGetErrorString(e));
+    }
+    sv_status st = SV_OK;
+    for (uint64_t off = 0; off < count && st == SV_OK; off += stage) {
+        const uint64_t c = std::min(stage, count - off);
+        e = svk::launch_probs(s->psi, s->dt, first + off, c, buf, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out_host + off, buf, c * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) st = hip_fail(e, "probs");
+    }
+    (void)hipFree(buf);
+    return st;
+}
+
+sv_status sv_norm_device(sv_state s, double *out_dev)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!out_dev) return fail(SV_EINVAL, "null output pointer");
+    DeviceScope ds(s->device);
+    const int tok = svk::prof_begin(s);
+    hipError_t e = svk::launch_norm(s->psi, s->n, s->dt, s->scratch, out_dev, s->stream);
+    svk::prof_end(s, tok, svk::KC_NORM, double(state_bytes(s)), 4.0 * std::ldexp(1.0, s->n));
+    if (e != hipSuccess) return hip_fail(e, "norm kernel launch");
+    return SV_OK;
+}
+
+sv_status sv_norm(sv_state s, double *out)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!out) return fail(SV_EINVAL, "null output pointer");
+    DeviceScope ds(s->device);
+    double *res = s->scratch + svk::kNormBlocks;
+    SV_HIP(svk::launch_norm(s->psi, s->n, s->dt, s->scratch, res, s->stream), "norm kernel launch");
+    SV_HIP(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm copy");
+    SV_HIP(hipStreamSynchronize(s->stream), "norm synchronize");
+    return SV_OK;
+}
+
+sv_status sv_copy_out(sv_state s, void *host_dst)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!host_dst) return fail(SV_EINVAL, "null host pointer");
+    DeviceScope ds(s->device);
+    SV_HIP(hipMemcpyAsync(host_dst, s->psi, state_bytes(s), hipMemcpyDeviceToHost, s->stream),
+           "state copy out");
+    SV_HIP(hipStreamSynchronize(s->stream), "copy-out synchronize");
+    return SV_OK;
+}
+
+sv_status sv_copy_in(sv_state s, const void *host_src)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!host_src) return fail(SV_EINVAL, "null host pointer");
+    DeviceScope ds(s->device);
+    SV_HIP(hipMemcpyAsync(s->psi, host_src, state_bytes(s), hipMemcpyHostToDevice, s->stream),
+           "state copy in");
+    SV_HIP(hipStreamSynchronize(s->stream), "copy-in synchronize");
+    return SV_OK;
+}
+
+sv_status sv_synchronize(sv_state s)
+{
+    if (sv_status st = check_handle(s)) return st;
+    DeviceScope ds(s->device);
+    SV_HIP(hipStreamSynchronize(s->stream), "stream synchronize");
+    return SV_OK;
+}
+
+}  // extern "C"

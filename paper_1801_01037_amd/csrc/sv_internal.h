@@ -1,0 +1,100 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+
+namespace svk {
+
+// Amplitudes per 16-byte access: one double2 (c128) or two float2 (c64).
+constexpr int kChunkBytes = 16;
+
+inline int elem_bytes(sv_dtype dt) { return dt == SV_C64 ? 8 : 16; }
+inline int chunk_log2(sv_dtype dt) { return dt == SV_C64 ? 1 : 0; }
+
+// A 2x2 complex matrix in FP64, row major (q11, q12, q21, q22) as (re, im).
+struct Mat2 {
+    double q[8];
+};
+
+// One term of a diagonal run: amplitudes whose index i has (i & mask) == val
+// are multiplied by e^{2 pi i turn / 2^64}. Turns add exactly in uint64 and
+// wrap modulo one full turn.
+struct DiagTerm {
+    uint64_t mask;
+    uint64_t val;
+    uint64_t turn;
+};
+constexpr int kMaxDiagTerms = 64;
+
+// ---- launchers (kernels_gate.hip) ----------------------------------------
+// All take the state pointer, qubit count and stream; they validate nothing.
+hipError_t launch_init(void *psi, int n, sv_dtype dt, uint64_t basis, hipStream_t st);
+// 2x2 on target t, optionally controlled by c (c < 0: none). swap_only: the
+// matrix is X (a pure exchange of the two amplitudes).
+hipError_t launch_pair(void *psi, int n, sv_dtype dt, int t, int c, const Mat2 &m,
+                       bool swap_only, hipStream_t st);
+// Product of the diagonal terms (at most kMaxDiagTerms).
+hipError_t launch_diag(void *psi, int n, sv_dtype dt, const DiagTerm *terms, int count,
+                       hipStream_t st);
+
+// ---- launchers (kernels_reduce.hip) --------------------------------------
+constexpr int kNormBlocks = 1024;
+// partials: kNormBlocks doubles of device scratch; out_dev: one double.
+hipError_t launch_norm(const void *psi, int n, sv_dtype dt, double *partials,
+                       double *out_dev, hipStream_t st);
+hipError_t launch_probs(const void *psi, sv_dtype dt, uint64_t first, uint64_t count,
+                        double *out_dev, hipStream_t st);
+
+// ---- host helpers (sv_api.hip) ---------------------------------------------
+uint64_t angle_to_turn(double theta);     // theta radians -> turns * 2^64 (mod 2^64)
+bool is_pauli_x(const double m[8]);
+bool is_phase_diag(const double m[8]);    // diag(1, e^{i phi}) with |e^{i phi}| == 1
+
+// ---- per-launch timing (profile.hip) ---------------------------------------
+// Kernel classes reported by sv_profile_read, in this order.
+enum KernelClass {
+    KC_INIT = 0, KC_PAIR, KC_PAIR_CTRL, KC_SWAP, KC_DIAG, KC_TILE, KC_DENSE, KC_NORM,
+    KC_PROBS, KC_BATCH, KC_COUNT
+};
+const char *class_name(int cls);
+
+struct ProfRec {
+    int cls;
+    double bytes;            // algorithmic bytes moved by the launch
+    double flops;            // algorithmic floating-point operations
+    hipEvent_t start, stop;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+}  // namespace svk
+
+struct sv_state_s {
+    void *psi = nullptr;
+    int n = 0;
+    sv_dtype dt = SV_C128;
+    hipStream_t stream = nullptr;
+    bool owned = false;
+    int device = 0;
+    double *scratch = nullptr;        // kNormBlocks + 1 doubles (norm partials + result)
+    svk::Profiler prof;
+};
+
+namespace svk {
+// Records a start event when profiling is on; returns a token for prof_end.
+int prof_begin(sv_state s);
+// Records the stop event of `token` (no-op for -1) with the launch's class,
+// algorithmic bytes and flops.
+void prof_end(sv_state s, int token, int cls, double bytes, double flops);
+void prof_release(sv_state s);
+}  // namespace svk

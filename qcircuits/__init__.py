@@ -223,3 +223,11 @@ def gate_qubits(g) -> tuple:
     if int(g["control"]) >= 0:
         return (int(g["control"]), int(g["target"]))
     return (int(g["target"]),)
+
+
+def random_state(n: int, seed: int) -> np.ndarray:
+    """A seeded normalised complex128 vector of 2^n amplitudes (i.i.d. normal
+    real and imaginary parts, scaled to unit 2-norm)."""
+    g = normals(seed, 2 << n)
+    psi = g[0::2] + 1j * g[1::2]
+    return psi / np.sqrt(np.sum(np.abs(psi) ** 2))
