@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate"], default="pergate",
+    ap.add_argument("--mode", choices=["fused", "pergate"], default="fused",
                     help="fused: SV_FUSE tile passes; pergate: one launch per gate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample")

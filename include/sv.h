@@ -165,6 +165,16 @@ sv_status sv_copy_in(sv_state s, const void *host_src);
 /* Waits for the handle's stream; SV_EDEVICE if queued work failed. */
 sv_status sv_synchronize(sv_state s);
 
+/* Plans a gate list for SV_FUSE on the host only (no device is touched) and
+ * reports its shape: *n_passes sweeps over the state, *n_groups register
+ * groups, *n_ops ops in execution order; gate_op[i] (n_gates entries, or
+ * NULL) receives the index of the last op that applies gate i. Gates are
+ * validated as in sv_run_circuit for an n_qubits register. flags must be
+ * SV_FUSE. Any out pointer may be NULL. */
+sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
+                          uint32_t flags, int32_t *gate_op, int32_t *n_passes, int32_t *n_groups,
+                          int32_t *n_ops);
+
 /* Per-kernel-class timing of the launches this handle queues, measured with
  * HIP events recorded on the handle's stream around each launch. */
 typedef struct {

@@ -22,7 +22,7 @@ __all__ = [
     "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
-    "StateVector", "LIB_PATH",
+    "sv_plan_inspect", "StateVector", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsv.so")
@@ -81,6 +81,8 @@ _SIGNATURES = {
     "sv_copy_in": ([_vp, _vp], _int),
     "sv_synchronize": ([_vp], _int),
     "sv_profile": ([_vp, _int], _int),
+    "sv_plan_inspect": ([_int, _int, _vp, _sz, _u32, _vp, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _int),
     "sv_profile_read": ([_vp, ctypes.POINTER(_ProfEntry), _int, ctypes.POINTER(_int)], _int),
 }
 
@@ -230,6 +232,19 @@ def sv_profile_read(h: int) -> dict:
     return {e.name.decode(): {"launches": int(e.launches), "total_ms": e.total_ms,
                               "bytes": e.bytes, "flops": e.flops}
             for e in buf[:min(cnt.value, 16)]}
+
+
+def sv_plan_inspect(n_qubits: int, dtype: int, gates: np.ndarray, flags: int = SV_FUSE):
+    """Host-only plan of a gate list: (gate_op array, n_passes, n_groups, n_ops)."""
+    g = np.ascontiguousarray(gates)
+    if g.dtype != GATE_DTYPE:
+        g = g.astype(GATE_DTYPE)
+    gate_op = np.empty(len(g), dtype=np.int32)
+    p, gr, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().sv_plan_inspect(n_qubits, dtype, g.ctypes.data if len(g) else None, len(g),
+                                 flags, gate_op.ctypes.data, ctypes.byref(p), ctypes.byref(gr),
+                                 ctypes.byref(o)))
+    return gate_op, p.value, gr.value, o.value
 
 
 class StateVector:

@@ -19,8 +19,11 @@ LIB = os.path.join(HERE, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
+# -simplifycfg-sink-common=false: sinking the common code of switch arms into
+# pointer selects over register arrays forces those arrays into scratch.
 CFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-simplifycfg-sink-common=false",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 

@@ -1,14 +1,496 @@
-// Circuit planning (placeholder until the tile pass lands).
+// Circuit planning for SV_FUSE: gate list -> tile passes.
+//
+// The paper applies one gate per sweep over the state (Algorithm 1). On one
+// GPU every sweep is bound by HBM, so the planner packs as many gates as it
+// legally can into one sweep:
+//   * a pass owns a set T of L tile qubits (index bits 0..nlow-1 always, for
+//     coalesced access, plus the targets met first in the gate list);
+//   * a non-diagonal gate joins the pass when its target is in T and it does
+//     not touch a qubit of a gate already left for a later pass (gates on
+//     disjoint qubits commute, so skipping ahead over them is exact);
+//   * a diagonal gate (controlled phase, or diag(1, e^{i phi})) joins any
+//     pass, and is held back inside the pass until the first later op that
+//     touches one of its qubits: diagonal gates commute with each other and
+//     with everything on other qubits, so held-back phases merge into few
+//     diagonal ops. Phases are kept as exact uint64 fractions of a turn;
+//   * inside a pass, consecutive ops whose targets fit in K register bits form
+//     a group (one LDS exchange per group).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <vector>
+
 #include "plan.h"
+#include "tile.h"
 
 namespace svk {
+namespace {
 
-sv_status plan_run(sv_state, const sv_gate *, size_t, uint32_t, std::string *err)
+// One gate after classification.
+struct Item {
+    int gate = -1;
+    bool diag = false;
+    int target = -1, control = -1;   // non-diagonal
+    bool swap = false;
+    double m[8] = {};
+    int pivot = -1, wbit = -1;       // diagonal: pivot bit, weight bit (-1: constant)
+    uint64_t turn = 0;
+    uint64_t qmask = 0;              // qubits touched
+};
+
+// A diagonal term: e^{2 pi i turn / 2^64} where bit p is 1 and (wbit < 0 or
+// bit wbit is 1).
+struct DTerm {
+    int wbit;
+    uint64_t turn;
+    int gate;
+};
+
+struct PPivot {
+    int p = -1;
+    std::vector<DTerm> terms;
+};
+
+struct POp {
+    int kind = TOP_U;
+    int target = -1, control = -1;
+    double m[8] = {};
+    std::vector<PPivot> piv;
+    std::vector<int> gates;
+};
+
+struct PGroup {
+    std::vector<int> S;   // local positions
+    std::vector<POp> ops;
+};
+
+struct PPass {
+    std::vector<int> T;   // global bits, ascending
+    std::vector<PGroup> groups;
+};
+
+struct TileGeom {
+    int L, K, nlow;
+    bool prefetch;
+};
+
+TileGeom geometry(int n, sv_dtype dt)
 {
-    *err = "fused execution is not built yet";
-    return SV_EUNSUPPORTED;
+    const bool c64 = dt == SV_C64;
+    TileGeom g;
+    int L = c64 ? kTileL64 : kTileL128;
+    int K = c64 ? kTileK64 : kTileK128;
+    int nlow = c64 ? 6 : 5;
+    g.prefetch = true;
+    // Tuning overrides (bounded to what the kernels are built for).
+    if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
+    if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
+    if (const char *e = std::getenv("SV_TILE_NLOW")) nlow = std::atoi(e);
+    if (const char *e = std::getenv("SV_TILE_PREFETCH")) g.prefetch = std::atoi(e) != 0;
+    g.L = std::min(n, L);
+    g.K = std::min(g.L, K);
+    if (g.L - g.K > 10) g.K = g.L - 10;   // at most 1024 threads
+    // At least one tile bit must stay free for other targets when the tile
+    // does not cover the whole register, or no pass could admit them.
+    g.nlow = std::max(0, std::min(nlow, g.L < n ? g.L - 1 : g.L));
+    return g;
 }
 
-void plan_release(sv_state) {}
+Item classify(const sv_gate &g, int idx)
+{
+    Item it;
+    it.gate = idx;
+    const uint64_t tb = uint64_t(1) << g.target;
+    if (g.kind == SV_G_CPHASE || (g.kind != SV_G_U && is_phase_diag(g.m)) ||
+        (g.kind == SV_G_U && is_phase_diag(g.m))) {
+        it.diag = true;
+        it.pivot = g.target;
+        it.wbit = g.kind == SV_G_U ? -1 : g.control;
+        const double theta = g.kind == SV_G_CPHASE ? g.m[0] : std::atan2(g.m[7], g.m[6]);
+        it.turn = angle_to_turn(theta);
+        it.qmask = tb | (it.wbit >= 0 ? uint64_t(1) << it.wbit : 0);
+        return it;
+    }
+    it.target = g.target;
+    it.control = g.kind == SV_G_U ? -1 : g.control;
+    it.swap = is_pauli_x(g.m);
+    std::memcpy(it.m, g.m, sizeof it.m);
+    it.qmask = tb | (it.control >= 0 ? uint64_t(1) << it.control : 0);
+    return it;
+}
+
+// Emits the pending diagonal terms that touch any qubit of `qm` (all of them
+// when qm is ~0) as diagonal ops appended to `ops`. Terms of one pivot stay
+// together in one op.
+void flush_diag(std::map<int, PPivot> &pending, uint64_t qm, std::vector<POp> &ops)
+{
+    std::vector<PPivot> out;
+    for (auto it = pending.begin(); it != pending.end();) {
+        PPivot &P = it->second;
+        PPivot part;
+        part.p = P.p;
+        const bool whole = (qm >> P.p) & 1;
+        std::vector<DTerm> keep;
+        for (const DTerm &t : P.terms) {
+            if (whole || (t.wbit >= 0 && ((qm >> t.wbit) & 1)))
+                part.terms.push_back(t);
+            else
+                keep.push_back(t);
+        }
+        if (!part.terms.empty()) out.push_back(std::move(part));
+        P.terms.swap(keep);
+        if (P.terms.empty())
+            it = pending.erase(it);
+        else
+            ++it;
+    }
+    for (size_t i = 0; i < out.size(); i += kTileMaxPivots) {
+        POp op;
+        op.kind = TOP_DIAG;
+        for (size_t j = i; j < std::min(out.size(), i + kTileMaxPivots); ++j) {
+            for (const DTerm &t : out[j].terms) op.gates.push_back(t.gate);
+            op.piv.push_back(std::move(out[j]));
+        }
+        ops.push_back(std::move(op));
+    }
+}
+
+// Splits the items into passes. *ok is false if some item could not be
+// placed (the geometry left no free tile bit); the plan is then incomplete.
+std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Item> &items, bool *ok)
+{
+    *ok = true;
+    std::vector<PPass> passes;
+    std::vector<Item> rem = items;
+    while (!rem.empty()) {
+        uint64_t Tm = (geo.nlow >= 64) ? ~uint64_t(0) : ((uint64_t(1) << geo.nlow) - 1);
+        int tcount = geo.nlow;
+        uint64_t blocked = 0;
+        std::vector<Item> next;
+        std::vector<POp> ops;
+        std::map<int, PPivot> pending;
+        for (const Item &it : rem) {
+            if (it.qmask & blocked) {
+                next.push_back(it);
+                blocked |= it.qmask;
+                continue;
+            }
+            if (it.diag) {
+                PPivot &P = pending[it.pivot];
+                P.p = it.pivot;
+                P.terms.push_back(DTerm{it.wbit, it.turn, it.gate});
+                continue;
+            }
+            if (!((Tm >> it.target) & 1)) {
+                if (tcount < geo.L) {
+                    Tm |= uint64_t(1) << it.target;
+                    ++tcount;
+                } else {
+                    next.push_back(it);
+                    blocked |= it.qmask;
+                    continue;
+                }
+            }
+            flush_diag(pending, it.qmask, ops);
+            POp op;
+            op.kind = it.swap ? TOP_SWAP : TOP_U;
+            op.target = it.target;
+            op.control = it.control;
+            std::memcpy(op.m, it.m, sizeof op.m);
+            op.gates.push_back(it.gate);
+            ops.push_back(std::move(op));
+        }
+        flush_diag(pending, ~uint64_t(0), ops);
+        if (ops.empty()) {   // no progress: refuse rather than drop gates
+            *ok = false;
+            break;
+        }
+        // Fill T up to L bits with the lowest unused qubits.
+        for (int b = 0; b < n && tcount < geo.L; ++b)
+            if (!((Tm >> b) & 1)) {
+                Tm |= uint64_t(1) << b;
+                ++tcount;
+            }
+        PPass pass;
+        for (int b = 0; b < n; ++b)
+            if ((Tm >> b) & 1) pass.T.push_back(b);
+        auto local = [&](int q) {
+            return int(std::lower_bound(pass.T.begin(), pass.T.end(), q) - pass.T.begin());
+        };
+        // Groups: consecutive ops whose targets fit in K register bits.
+        PGroup cur;
+        for (POp &op : ops) {
+            if (op.kind != TOP_DIAG) {
+                const int p = local(op.target);
+                const bool have = std::find(cur.S.begin(), cur.S.end(), p) != cur.S.end();
+                if (!have && int(cur.S.size()) >= geo.K) {
+                    pass.groups.push_back(std::move(cur));
+                    cur = PGroup();
+                }
+                if (std::find(cur.S.begin(), cur.S.end(), p) == cur.S.end()) cur.S.push_back(p);
+            }
+            cur.ops.push_back(std::move(op));
+        }
+        if (!cur.ops.empty()) pass.groups.push_back(std::move(cur));
+        for (PGroup &g : pass.groups) {
+            // Pad S with the highest unused local bits so the threads of a
+            // wave differ in low local bits (contiguous LDS slots).
+            for (int b = geo.L - 1; b >= 0 && int(g.S.size()) < geo.K; --b)
+                if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) g.S.push_back(b);
+            std::sort(g.S.begin(), g.S.end());
+        }
+        passes.push_back(std::move(pass));
+        rem.swap(next);
+    }
+    return passes;
+}
+
+// ---- flattening and execution ---------------------------------------------
+
+struct Flat {
+    std::vector<TileGroup> groups;
+    std::vector<TileOp> ops;
+    std::vector<TilePivot> pivots;
+    std::vector<TileArgs> args;   // one per pass (pointers patched after upload)
+    std::vector<double> flops;    // per pass
+};
+
+Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
+{
+    Flat f;
+    for (const PPass &pass : passes) {
+        TileArgs a{};
+        a.L = geo.L;
+        a.nlow = geo.nlow;
+        uint64_t Tm = 0;
+        for (int b : pass.T) Tm |= uint64_t(1) << b;
+        const uint64_t all = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+        a.tmask = Tm;
+        a.omask = all & ~Tm;
+        a.nnon = n - geo.L;
+        a.ntiles = uint64_t(1) << a.nnon;
+        a.group0 = int(f.groups.size());
+        a.ngroups = int(pass.groups.size());
+        a.has_diag = 0;
+        double flops = 0;
+        auto local = [&](int q) {
+            return int(std::lower_bound(pass.T.begin(), pass.T.end(), q) - pass.T.begin());
+        };
+        const double N = std::ldexp(1.0, n);
+        for (const PGroup &g : pass.groups) {
+            TileGroup tg{};
+            for (int k = 0; k < geo.K; ++k) tg.s[k] = g.S[k];
+            int nn = 0;
+            for (int b = 0; b < geo.L; ++b)
+                if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) tg.ns[nn++] = b;
+            tg.op0 = int(f.ops.size());
+            tg.nops = int(g.ops.size());
+            for (const POp &op : g.ops) {
+                TileOp to{};
+                to.kind = op.kind;
+                to.lctrl = -1;
+                to.octrl = -1;
+                if (op.kind == TOP_DIAG) {
+                    a.has_diag = 1;
+                    to.piv0 = int(f.pivots.size());
+                    to.npiv = int(op.piv.size());
+                    for (const PPivot &P : op.piv) {
+                        TilePivot tp{};
+                        tp.lpivot = ((Tm >> P.p) & 1) ? local(P.p) : -1;
+                        tp.opivot = ((Tm >> P.p) & 1) ? -1 : P.p;
+                        std::map<int, uint64_t> outside;
+                        for (const DTerm &t : P.terms) {
+                            if (t.wbit < 0) tp.w0 += t.turn;
+                            else if ((Tm >> t.wbit) & 1) tp.wl[local(t.wbit)] += t.turn;
+                            else outside[t.wbit] += t.turn;
+                        }
+                        for (const auto &kv : outside) {
+                            tp.obit[tp.nout] = kv.first;
+                            tp.ow[tp.nout] = kv.second;
+                            ++tp.nout;
+                        }
+                        f.pivots.push_back(tp);
+                        flops += 1.5 * N * double(P.terms.size());
+                    }
+                } else {
+                    const int p = local(op.target);
+                    to.pj = int(std::find(g.S.begin(), g.S.end(), p) - g.S.begin());
+                    if (op.control >= 0) {
+                        if ((Tm >> op.control) & 1) to.lctrl = local(op.control);
+                        else to.octrl = op.control;
+                    }
+                    std::memcpy(to.m, op.m, sizeof to.m);
+                    for (int k = 0; k < 8; ++k) to.mf[k] = float(op.m[k]);
+                    if (op.kind == TOP_U) flops += (op.control >= 0 ? 7.0 : 14.0) * N;
+                }
+                f.ops.push_back(to);
+            }
+            f.groups.push_back(tg);
+        }
+        f.args.push_back(a);
+        f.flops.push_back(flops);
+    }
+    return f;
+}
+
+template <typename A>
+void fill_phase_table(A *tab)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < 256; ++k) {
+        const double a1 = two_pi * (double(k) / 256.0);
+        const double a2 = two_pi * (double(k) / 65536.0);
+        tab[k].x = std::cos(a1);
+        tab[k].y = std::sin(a1);
+        tab[256 + k].x = std::cos(a2);
+        tab[256 + k].y = std::sin(a2);
+    }
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// Device resources of the planner, owned by a state handle.
+struct PlanCache {
+    void *dev = nullptr;
+    size_t dev_cap = 0;
+    void *host = nullptr;       // pinned staging
+    size_t host_cap = 0;
+    hipEvent_t staged = nullptr;
+};
+
+static PlanCache *cache_of(sv_state s)
+{
+    if (!s->plan) s->plan = new PlanCache();
+    return static_cast<PlanCache *>(s->plan);
+}
+
+sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
+                   std::string *err)
+{
+    if (flags & (SV_FUSE_DENSE | SV_GRAPH)) {
+        *err = "SV_FUSE_DENSE and SV_GRAPH are not built yet";
+        return SV_EUNSUPPORTED;
+    }
+    const TileGeom geo = geometry(s->n, s->dt);
+    std::vector<Item> items;
+    items.reserve(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
+    bool ok = true;
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
+    if (!ok) {
+        *err = "planner could not place every gate with this tile geometry";
+        return SV_EUNSUPPORTED;
+    }
+    Flat f = flatten(s->n, geo, passes);
+
+    const bool c64 = s->dt == SV_C64;
+    const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
+    const size_t off_groups = 0;
+    const size_t off_ops = align_up(off_groups + f.groups.size() * sizeof(TileGroup), 256);
+    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
+    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
+    const size_t total = align_up(off_tab + tab_bytes, 256);
+
+    PlanCache *pc = cache_of(s);
+    hipError_t e = hipSuccess;
+    if (pc->staged) {
+        e = hipEventSynchronize(pc->staged);   // staging buffer free again
+        if (e != hipSuccess) { *err = hipGetErrorString(e); return SV_EDEVICE; }
+    } else if ((e = hipEventCreateWithFlags(&pc->staged, hipEventDisableTiming)) != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return SV_EDEVICE;
+    }
+    if (pc->host_cap < total) {
+        if (pc->host) (void)hipHostFree(pc->host);
+        pc->host = nullptr;
+        pc->host_cap = 0;
+        if ((e = hipHostMalloc(&pc->host, total, 0)) != hipSuccess) {
+            *err = "pinned staging allocation failed";
+            return SV_ENOMEM;
+        }
+        pc->host_cap = total;
+    }
+    if (pc->dev_cap < total) {
+        if (pc->dev) (void)hipFree(pc->dev);   // hipFree waits for work that may use it
+        pc->dev = nullptr;
+        pc->dev_cap = 0;
+        if ((e = hipMalloc(&pc->dev, total)) != hipSuccess) {
+            (void)hipGetLastError();
+            *err = "device plan allocation failed";
+            return SV_ENOMEM;
+        }
+        pc->dev_cap = total;
+    }
+    char *h = static_cast<char *>(pc->host);
+    std::memcpy(h + off_groups, f.groups.data(), f.groups.size() * sizeof(TileGroup));
+    std::memcpy(h + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
+    std::memcpy(h + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
+    if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + off_tab));
+    else fill_phase_table(reinterpret_cast<double2 *>(h + off_tab));
+    e = hipMemcpyAsync(pc->dev, pc->host, total, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(pc->staged, s->stream);
+    if (e != hipSuccess) { *err = hipGetErrorString(e); return SV_EDEVICE; }
+
+    char *d = static_cast<char *>(pc->dev);
+    const double bytes = 2.0 * std::ldexp(1.0, s->n) * elem_bytes(s->dt);
+    for (size_t p = 0; p < f.args.size(); ++p) {
+        TileArgs a = f.args[p];
+        a.psi = s->psi;
+        a.groups = reinterpret_cast<const TileGroup *>(d + off_groups);
+        a.ops = reinterpret_cast<const TileOp *>(d + off_ops);
+        a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
+        a.phase_tab = d + off_tab;
+        const int tok = prof_begin(s);
+        e = launch_tile(a, geo.K, c64, geo.prefetch, s->stream);
+        prof_end(s, tok, KC_TILE, bytes, f.flops[p]);
+        if (e != hipSuccess) { *err = std::string("tile launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
+    }
+    return SV_OK;
+}
+
+void plan_release(sv_state s)
+{
+    if (!s->plan) return;
+    PlanCache *pc = static_cast<PlanCache *>(s->plan);
+    if (pc->staged) (void)hipEventSynchronize(pc->staged);
+    if (pc->dev) (void)hipFree(pc->dev);
+    if (pc->host) (void)hipHostFree(pc->host);
+    if (pc->staged) (void)hipEventDestroy(pc->staged);
+    delete pc;
+    s->plan = nullptr;
+}
+
+// Host-only view of a plan, for inspection and tests.
+int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32_t *gate_op,
+                 int32_t *n_passes, int32_t *n_groups, int32_t *n_ops)
+{
+    const TileGeom geo = geometry(n, dt);
+    std::vector<Item> items;
+    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
+    bool ok = true;
+    const std::vector<PPass> passes = plan_passes(n, geo, items, &ok);
+    if (!ok) return -1;
+    int32_t seq = 0, groups = 0;
+    if (gate_op)
+        for (size_t i = 0; i < n_gates; ++i) gate_op[i] = -1;
+    for (const PPass &p : passes) {
+        for (const PGroup &g : p.groups) {
+            ++groups;
+            for (const POp &op : g.ops) {
+                if (gate_op)
+                    for (int gi : op.gates) gate_op[gi] = std::max(gate_op[gi], seq);
+                ++seq;
+            }
+        }
+    }
+    if (n_passes) *n_passes = int32_t(passes.size());
+    if (n_groups) *n_groups = groups;
+    if (n_ops) *n_ops = seq;
+    return 0;
+}
 
 }  // namespace svk

@@ -418,6 +418,24 @@ sv_status sv_copy_in(sv_state s, const void *host_src)
     return SV_OK;
 }
 
+sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
+                          uint32_t flags, int32_t *gate_op, int32_t *n_passes, int32_t *n_groups,
+                          int32_t *n_ops)
+{
+    if (!valid_dtype(dtype)) return fail(SV_EINVAL, "unknown dtype %d", int(dtype));
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [1, 34]", n_qubits);
+    if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
+    if (flags != SV_FUSE) return fail(SV_EUNSUPPORTED, "only SV_FUSE plans can be inspected");
+    sv_state_s probe;
+    probe.n = n_qubits;
+    probe.dt = dtype;
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
+    if (svk::plan_inspect(n_qubits, dtype, gates, n_gates, gate_op, n_passes, n_groups, n_ops) != 0)
+        return fail(SV_EUNSUPPORTED, "planner could not place every gate with this tile geometry");
+    return SV_OK;
+}
+
 sv_status sv_synchronize(sv_state s)
 {
     if (sv_status st = check_handle(s)) return st;

@@ -88,6 +88,7 @@ struct sv_state_s {
     int device = 0;
     double *scratch = nullptr;        // kNormBlocks + 1 doubles (norm partials + result)
     svk::Profiler prof;
+    void *plan = nullptr;             // planner buffers (plan.hip)
 };
 
 namespace svk {

@@ -1,0 +1,87 @@
+// Device-visible description of a fused tile pass (built by the planner,
+// executed by k_tile).
+//
+// A pass fixes a set T of L "tile" qubits. Work-group g owns the 2^L
+// amplitudes whose index bits outside T equal the bits of g; it loads them
+// into LDS, applies a program of ops, and writes them back, so the pass costs
+// one read and one write of the state however many gates it holds. The
+// program is a list of groups; in a group each thread holds 2^K amplitudes
+// in registers (the K tile bits S of the group enumerated, the other L-K tile
+// bits fixed by the thread id), so every op whose target is in S is applied
+// in registers, with one LDS exchange per group.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace svk {
+
+constexpr int kTileMaxL = 13;     // tile bits (c128: 12, c64: 13)
+constexpr int kTileMaxK = 4;      // register bits per group
+constexpr int kTileL128 = 12, kTileK128 = 4;   // 64 KiB of complex128 per tile, 256 threads
+constexpr int kTileL64 = 13, kTileK64 = 4;     // 64 KiB of complex64 per tile, 512 threads
+constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
+
+enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2 };
+
+// A diagonal op multiplies each amplitude by e^{2 pi i T / 2^64}, where T is
+// an exact uint64 sum (mod one full turn) over the op's pivots:
+//     T(i) = sum_p [bit p of i is 1] * (w0_p + sum_b [bit b of i is 1] * w_p[b]).
+// Controlled-phase gates with target p and controls b, and one-qubit phases
+// diag(1, e^{i phi}) on p (as w0_p), are all of this form.
+struct TilePivot {
+    int32_t lpivot;        // pivot as a local tile bit, or -1
+    int32_t opivot;        // pivot as a global bit outside the tile, or -1
+    int32_t nout;          // weights on global bits outside the tile
+    int32_t pad;
+    uint64_t w0;
+    uint64_t wl[kTileMaxL];   // weight of each local tile bit
+    int32_t obit[40];         // outside bits with a weight
+    uint64_t ow[40];          // their weights
+};
+constexpr int kTileMaxPivots = 8;
+
+struct TileOp {
+    int32_t kind;
+    int32_t pj;        // TOP_U / TOP_SWAP: target as a position in the group's S
+    int32_t lctrl;     // control as a local tile bit, or -1
+    int32_t octrl;     // control as a global index bit outside the tile, or -1
+    int32_t piv0;      // TOP_DIAG: first pivot
+    int32_t npiv;      // TOP_DIAG: number of pivots (<= kTileMaxPivots)
+    int32_t pad0, pad1;
+    double m[8];       // 2x2 in FP64
+    float mf[8];       // the same rounded to FP32 (complex64 states)
+};
+
+struct TileGroup {
+    int32_t s[kTileMaxK];          // local tile bits held in registers, ascending
+    int32_t ns[kTileMaxL];         // the other L-K local bits, ascending
+    int32_t op0, nops;
+};
+
+struct TileArgs {
+    void *psi;
+    const TileGroup *groups;
+    const TileOp *ops;
+    const TilePivot *pivots;
+    const void *phase_tab;         // e^{2 pi i k/256} then e^{2 pi i k/65536}, k < 256
+    uint64_t tmask;                // index bits of the tile (L of them)
+    uint64_t omask;                // the other index bits of the register
+    uint64_t ntiles;               // 2^nnon
+    int32_t L;                     // tile bits
+    int32_t nlow;                  // tile bits 0..nlow-1 are index bits 0..nlow-1
+    int32_t nnon;                  // index bits outside the tile
+    int32_t group0, ngroups;
+    int32_t has_diag;              // the pass holds diagonal ops (load phase_tab)
+};
+
+// Dynamic LDS of one work-group: padded tile plus the phase table.
+size_t tile_lds_bytes(bool c64, int L, bool diag);
+// Launches one pass: 2^(L-K) threads per work-group; each work-group walks
+// tiles g = blockIdx.x, blockIdx.x + gridDim.x, ... below 2^nnon.
+// prefetch: load the next tile into registers while the current one is processed.
+hipError_t launch_tile(const TileArgs &a, int K, bool c64, bool prefetch, hipStream_t st);
+
+}  // namespace svk

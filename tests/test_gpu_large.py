@@ -33,7 +33,7 @@ def _gather(st, idx):
     return st.tensor[t].cpu().numpy().astype(np.complex128)
 
 
-@pytest.mark.parametrize("flags", [0], ids=["per-gate"])
+@pytest.mark.parametrize("flags", [0, sv.SV_FUSE], ids=["per-gate", "fused"])
 @pytest.mark.parametrize("dtype", [sv.SV_C128, sv.SV_C64], ids=["c128", "c64"])
 def test_qft_30_qubits_matches_closed_form(dtype, flags):
     x = qc.random_basis_index(N30, 2024)
@@ -53,15 +53,15 @@ def test_qft_30_qubits_matches_closed_form(dtype, flags):
         assert abs(nrm - 1.0) <= 1e-5
 
 
+@pytest.mark.parametrize("flags", [0, sv.SV_FUSE], ids=["per-gate", "fused"])
 @pytest.mark.parametrize("dtype", [sv.SV_C128, sv.SV_C64], ids=["c128", "c64"])
-def test_mirror_30_qubits_returns_to_start(dtype):
-    import torch
+def test_mirror_30_qubits_returns_to_start(dtype, flags):
     g = qc.layer_circuit(N30, 20, 11)
     x = qc.random_basis_index(N30, 12)
     with sv.StateVector(N30, dtype, basis_index=x) as st:
-        st.run(g)
+        st.run(g, flags)
         mid_norm = st.norm()
-        st.run(qc.inverse_circuit(g))
+        st.run(qc.inverse_circuit(g), flags)
         t = st.tensor
         at_x = complex(t[x].item())
         t[x] = 0
@@ -76,12 +76,13 @@ def test_mirror_30_qubits_returns_to_start(dtype):
         assert abs(mid_norm - 1.0) <= 1e-5
 
 
-def test_random_circuit_30_qubits_c64_against_c128():
+@pytest.mark.parametrize("flags", [0, sv.SV_FUSE], ids=["per-gate", "fused"])
+def test_random_circuit_30_qubits_c64_against_c128(flags):
     import torch
     g = qc.layer_circuit(N30, 20, 1)
     with sv.StateVector(N30, sv.SV_C128) as a, sv.StateVector(N30, sv.SV_C64) as b:
-        a.run(g)
-        b.run(g)
+        a.run(g, flags)
+        b.run(g, flags)
         torch.cuda.synchronize()
         diff = (b.tensor.to(torch.complex128) - a.tensor).norm().item()
         ref = a.tensor.norm().item()
@@ -89,3 +90,14 @@ def test_random_circuit_30_qubits_c64_against_c128():
     assert abs(na - 1.0) <= 1e-12
     assert abs(nb - 1.0) <= 1e-5
     assert diff / ref <= c64_rel_tol(len(g))
+
+
+def test_random_circuit_30_qubits_fused_against_per_gate():
+    import torch
+    g = qc.layer_circuit(N30, 20, 1)
+    with sv.StateVector(N30, sv.SV_C128) as a, sv.StateVector(N30, sv.SV_C128) as b:
+        a.run(g, 0)
+        b.run(g, sv.SV_FUSE)
+        torch.cuda.synchronize()
+        err = (a.tensor - b.tensor).abs().max().item()
+    assert err <= C128_MAX_ABS

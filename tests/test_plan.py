@@ -1,0 +1,95 @@
+"""The SV_FUSE planner on the host: every gate is applied exactly once, and any
+two gates that share a qubit keep their order unless both are diagonal
+(diagonal gates commute with each other). Runs without a GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_1801_01037_amd as sv
+import qcircuits as qc
+
+
+def _is_diag(g):
+    if int(g["kind"]) == qc.G_CPHASE:
+        return True
+    m = g["m"]
+    if not (m[0] == 1 and m[1] == 0 and m[2] == 0 and m[3] == 0 and m[4] == 0 and m[5] == 0):
+        return False
+    return abs(m[6] ** 2 + m[7] ** 2 - 1.0) <= 4e-16
+
+
+def _qubits(g):
+    return {int(g["target"])} | ({int(g["control"])} if int(g["control"]) >= 0 else set())
+
+
+def check_plan_order(n, dtype, gates):
+    gate_op, passes, groups, ops = sv.sv_plan_inspect(n, dtype, gates)
+    assert (gate_op >= 0).all() and (gate_op < ops).all()
+    diag = np.array([_is_diag(g) for g in gates])
+    by_qubit = {}
+    for i, g in enumerate(gates):
+        for q in _qubits(g):
+            by_qubit.setdefault(q, []).append(i)
+    for q, idx in by_qubit.items():
+        for a in range(len(idx)):
+            for b in range(a + 1, len(idx)):
+                i, j = idx[a], idx[b]
+                if diag[i] and diag[j]:
+                    continue
+                assert gate_op[i] < gate_op[j], (q, i, j, gate_op[i], gate_op[j])
+    nondiag_ops = gate_op[~diag]
+    assert len(set(nondiag_ops.tolist())) == len(nondiag_ops)   # one op per such gate
+    return passes, groups, ops
+
+
+def mixed_circuit(n, count, seed):
+    rng = np.random.default_rng(seed)
+    su2 = qc.haar_su2(seed, count)
+    out = []
+    for i in range(count):
+        kind = int(rng.integers(0, 6)) if n > 1 else 0
+        t = int(rng.integers(0, n))
+        c = int(rng.integers(0, n - 1)) if n > 1 else 0
+        c = c + 1 if c >= t else c
+        if kind == 0:
+            out.append(qc.gate_u(t, su2[i]))
+        elif kind == 1:
+            out.append(qc.gate_cu(c, t, su2[i]))
+        elif kind == 2:
+            out.append(qc.gate_cnot(c, t))
+        elif kind == 3:
+            out.append(qc.gate_cphase(c, t, float(rng.uniform(-7, 7))))
+        elif kind == 4:
+            ph = float(rng.uniform(-3, 3))
+            out.append(qc.gate_u(t, (1, 0, 0, 0, 0, 0, math.cos(ph), math.sin(ph))))
+        else:
+            out.append(qc.gate_u(t, qc.X_MATRIX))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("dtype", [sv.SV_C128, sv.SV_C64], ids=["c128", "c64"])
+def test_workload_plans_are_legal(dtype):
+    shapes = {}
+    for name, n, g in [("qft30", 30, qc.qft_circuit(30)),
+                       ("layers30", 30, qc.layer_circuit(30, 20, 1)),
+                       ("layers_qft16", 16, qc.workload_layers_qft(16, 100, 0)),
+                       ("layers34", 34, qc.layer_circuit(34, 10, 1))]:
+        shapes[name] = check_plan_order(n, dtype, g)
+    assert shapes["qft30"][0] <= 6          # QFT(30) needs only a few sweeps
+    assert shapes["layers30"][0] <= 40
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 13, 17, 22])
+def test_mixed_circuit_plans_are_legal(n):
+    for seed in range(3):
+        g = mixed_circuit(n, 300, seed + 100 * n)
+        for dtype in (sv.SV_C128, sv.SV_C64):
+            check_plan_order(n, dtype, g)
+
+
+def test_plan_rejects_bad_gates():
+    with pytest.raises(sv.SVError):
+        sv.sv_plan_inspect(4, sv.SV_C128, qc.gate_cnot(2, 2))
+    with pytest.raises(sv.SVError):
+        sv.sv_plan_inspect(4, sv.SV_C128, qc.gate_u(4, qc.X_MATRIX))
