@@ -175,6 +175,16 @@ sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, si
                           uint32_t flags, int32_t *gate_op, int32_t *n_passes, int32_t *n_groups,
                           int32_t *n_ops);
 
+/* Plans a gate list for SV_FUSE_DENSE on the host only: *n_blocks blocks of
+ * five qubits each. For the first `cap` blocks, block_masks[b] (may be NULL)
+ * receives the block's five index bits and block_mats (may be NULL; cap*2048
+ * doubles) its 32x32 complex matrix, row major, interleaved (re, im); local
+ * index bit k of the matrix is the k-th lowest bit of the mask. The gates of
+ * the list, applied in order, equal the blocks' matrices applied in order. */
+sv_status sv_plan_dense_inspect(int n_qubits, const sv_gate *gates, size_t n_gates,
+                                uint64_t *block_masks, double *block_mats, int32_t cap,
+                                int32_t *n_blocks);
+
 /* Per-kernel-class timing of the launches this handle queues, measured with
  * HIP events recorded on the handle's stream around each launch. */
 typedef struct {

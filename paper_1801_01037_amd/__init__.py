@@ -22,7 +22,7 @@ __all__ = [
     "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
-    "sv_plan_inspect", "StateVector", "LIB_PATH",
+    "sv_plan_inspect", "sv_plan_dense_inspect", "StateVector", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsv.so")
@@ -83,6 +83,8 @@ _SIGNATURES = {
     "sv_profile": ([_vp, _int], _int),
     "sv_plan_inspect": ([_int, _int, _vp, _sz, _u32, _vp, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _int),
+    "sv_plan_dense_inspect": ([_int, _vp, _sz, _vp, _vp, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32)], _int),
     "sv_profile_read": ([_vp, ctypes.POINTER(_ProfEntry), _int, ctypes.POINTER(_int)], _int),
 }
 
@@ -245,6 +247,22 @@ def sv_plan_inspect(n_qubits: int, dtype: int, gates: np.ndarray, flags: int = S
                                  flags, gate_op.ctypes.data, ctypes.byref(p), ctypes.byref(gr),
                                  ctypes.byref(o)))
     return gate_op, p.value, gr.value, o.value
+
+
+def sv_plan_dense_inspect(n_qubits: int, gates: np.ndarray, cap: int | None = None):
+    """Host-only dense-block plan: (block masks, complex (nb, 32, 32) matrices)."""
+    g = np.ascontiguousarray(gates)
+    if g.dtype != GATE_DTYPE:
+        g = g.astype(GATE_DTYPE)
+    nb = ctypes.c_int32()
+    ptr = g.ctypes.data if len(g) else None
+    _check(lib().sv_plan_dense_inspect(n_qubits, ptr, len(g), None, None, 0, ctypes.byref(nb)))
+    cap = nb.value if cap is None else min(cap, nb.value)
+    masks = np.zeros(cap, dtype=np.uint64)
+    mats = np.zeros((cap, 32, 32), dtype=np.complex128)
+    _check(lib().sv_plan_dense_inspect(n_qubits, ptr, len(g), masks.ctypes.data, mats.ctypes.data,
+                                       cap, ctypes.byref(nb)))
+    return masks, mats
 
 
 class StateVector:

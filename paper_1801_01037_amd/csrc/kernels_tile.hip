@@ -99,7 +99,7 @@ __device__ __forceinline__ AmpT<C64> turn_phase(uint64_t T, const AmpT<C64> *tab
     return cmul(cmul(e1, e2), e3);
 }
 
-template <bool C64, int K, int PJ, bool SWAP>
+template <bool C64, int K, int PJ, bool SWAP, bool CTRL>
 __device__ __forceinline__ void pair_pj(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
                                         COp &op)
 {
@@ -122,7 +122,6 @@ __device__ __forceinline__ void pair_pj(AmpT<C64> (&v)[1 << K], const uint32_t (
         if (r & (1 << PJ)) continue;
         constexpr int bit = 1 << PJ;
         const int r1 = r | bit;
-        const bool on = lc < 0 || ((li[r] >> lc) & 1u);
         const A a = v[r], b = v[r1];
         A na, nb;
         if constexpr (SWAP) {
@@ -134,21 +133,26 @@ __device__ __forceinline__ void pair_pj(AmpT<C64> (&v)[1 << K], const uint32_t (
             nb.x = m4 * a.x - m5 * a.y + m6 * b.x - m7 * b.y;
             nb.y = m4 * a.y + m5 * a.x + m6 * b.y + m7 * b.x;
         }
-        v[r] = on ? na : a;
-        v[r1] = on ? nb : b;
+        if constexpr (CTRL) {
+            const bool on = (li[r] >> lc) & 1u;
+            v[r] = on ? na : a;
+            v[r1] = on ? nb : b;
+        } else {
+            v[r] = na;
+            v[r1] = nb;
+        }
     }
 }
 
-template <bool C64, int K, bool SWAP>
+template <bool C64, int K, bool SWAP, bool CTRL>
 __device__ __forceinline__ void apply_pair(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
                                            COp &op)
 {
     switch (op.pj) {
-    case 0: pair_pj<C64, K, 0, SWAP>(v, li, op); break;
-    case 1: if constexpr (K > 1) pair_pj<C64, K, 1, SWAP>(v, li, op); break;
-    case 2: if constexpr (K > 2) pair_pj<C64, K, 2, SWAP>(v, li, op); break;
-    case 3: if constexpr (K > 3) pair_pj<C64, K, 3, SWAP>(v, li, op); break;
-    case 4: if constexpr (K > 4) pair_pj<C64, K, 4, SWAP>(v, li, op); break;
+    case 0: pair_pj<C64, K, 0, SWAP, CTRL>(v, li, op); break;
+    case 1: if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(v, li, op); break;
+    case 2: if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(v, li, op); break;
+    case 3: if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(v, li, op); break;
     default: break;
     }
 }
@@ -265,10 +269,14 @@ __device__ __forceinline__ void tile_body(const TileArgs a)
                     continue;
                 }
                 if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) continue;
-                if (op.kind == TOP_SWAP)
-                    apply_pair<C64, K, true>(v, li, op);
-                else
-                    apply_pair<C64, K, false>(v, li, op);
+                const bool ctrl = op.lctrl >= 0;
+                if (op.kind == TOP_SWAP) {
+                    if (ctrl) apply_pair<C64, K, true, true>(v, li, op);
+                    else apply_pair<C64, K, true, false>(v, li, op);
+                } else {
+                    if (ctrl) apply_pair<C64, K, false, true>(v, li, op);
+                    else apply_pair<C64, K, false, false>(v, li, op);
+                }
             }
 #pragma unroll
             for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];

@@ -17,6 +17,8 @@ void plan_release(sv_state s);
 
 // Plans without a device: gate_op[i] (n_gates entries, may be NULL) receives
 // the index, in execution order, of the last op that carries gate i.
+int plan_dense_inspect(int n, const sv_gate *gates, size_t n_gates, uint64_t *masks,
+                       double *mats, int cap);
 int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32_t *gate_op,
                  int32_t *n_passes, int32_t *n_groups, int32_t *n_ops);
 

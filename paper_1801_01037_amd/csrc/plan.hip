@@ -19,9 +19,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <vector>
 
+#include "dense.h"
 #include "plan.h"
 #include "tile.h"
 
@@ -83,7 +85,7 @@ TileGeom geometry(int n, sv_dtype dt)
     int L = c64 ? kTileL64 : kTileL128;
     int K = c64 ? kTileK64 : kTileK128;
     int nlow = c64 ? 6 : 5;
-    g.prefetch = true;
+    g.prefetch = false;   // measured faster: the prefetch registers cost occupancy
     // Tuning overrides (bounded to what the kernels are built for).
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
@@ -351,6 +353,103 @@ void fill_phase_table(A *tab)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// ---- dense 5-qubit blocks (SV_FUSE_DENSE) ------------------------------------
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+uint64_t gate_qmask(const sv_gate &g)
+{
+    uint64_t m = uint64_t(1) << g.target;
+    if (g.kind != SV_G_U) m |= uint64_t(1) << g.control;
+    return m;
+}
+
+struct DBlock {
+    uint64_t qmask = 0;
+    std::vector<int> gates;
+};
+
+// Groups the gates into blocks of at most five qubits. A gate joins the open
+// block when the union stays within five qubits and it touches no qubit of a
+// gate already left for a later block (those commute past it).
+std::vector<DBlock> plan_dense(int n, const sv_gate *g, size_t ng)
+{
+    std::vector<DBlock> blocks;
+    std::vector<int> rem(ng);
+    for (size_t i = 0; i < ng; ++i) rem[i] = int(i);
+    while (!rem.empty()) {
+        DBlock b;
+        uint64_t blocked = 0;
+        std::vector<int> next;
+        for (int i : rem) {
+            const uint64_t qm = gate_qmask(g[i]);
+            if ((qm & blocked) || popcount64(b.qmask | qm) > 5) {
+                next.push_back(i);
+                blocked |= qm;
+                continue;
+            }
+            b.qmask |= qm;
+            b.gates.push_back(i);
+        }
+        // Pad to five qubits with the highest unused ones, so that the low
+        // index bits stay in the column index (coalesced columns).
+        for (int q = n - 1; q >= 0 && popcount64(b.qmask) < 5; --q) b.qmask |= uint64_t(1) << q;
+        blocks.push_back(std::move(b));
+        rem.swap(next);
+    }
+    return blocks;
+}
+
+// The block's 32x32 complex matrix (FP64), built by applying each gate's
+// stride update to the 32 columns of the identity, then written as the real
+// 64x64 form [[Re, -Im], [Im, Re]] in row-major order.
+template <typename R>
+void block_matrix(const DBlock &b, const sv_gate *g, R *out)
+{
+    int pos[64];
+    int k = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((b.qmask >> q) & 1) pos[q] = k++;
+    static thread_local double re[32][32], im[32][32];   // [row][column]
+    for (int i = 0; i < 32; ++i)
+        for (int j = 0; j < 32; ++j) {
+            re[i][j] = i == j ? 1.0 : 0.0;
+            im[i][j] = 0.0;
+        }
+    for (int gi : b.gates) {
+        const sv_gate &G = g[gi];
+        double m[8];
+        if (G.kind == SV_G_CPHASE) {
+            const double c = std::cos(G.m[0]), s_ = std::sin(G.m[0]);
+            const double d[8] = {1, 0, 0, 0, 0, 0, c, s_};
+            std::memcpy(m, d, sizeof m);
+        } else {
+            std::memcpy(m, G.m, sizeof m);
+        }
+        const int t = pos[G.target];
+        const int c = G.kind == SV_G_U ? -1 : pos[G.control];
+        for (int col = 0; col < 32; ++col)
+            for (int i0 = 0; i0 < 32; ++i0) {
+                if ((i0 >> t) & 1) continue;
+                if (c >= 0 && !((i0 >> c) & 1)) continue;
+                const int i1 = i0 | (1 << t);
+                const double ar = re[i0][col], ai = im[i0][col];
+                const double br = re[i1][col], bi = im[i1][col];
+                re[i0][col] = m[0] * ar - m[1] * ai + m[2] * br - m[3] * bi;
+                im[i0][col] = m[0] * ai + m[1] * ar + m[2] * bi + m[3] * br;
+                re[i1][col] = m[4] * ar - m[5] * ai + m[6] * br - m[7] * bi;
+                im[i1][col] = m[4] * ai + m[5] * ar + m[6] * bi + m[7] * br;
+            }
+    }
+    for (int i = 0; i < 32; ++i)
+        for (int j = 0; j < 32; ++j) {
+            out[i * 64 + j] = R(re[i][j]);
+            out[i * 64 + 32 + j] = R(-im[i][j]);
+            out[(32 + i) * 64 + j] = R(im[i][j]);
+            out[(32 + i) * 64 + 32 + j] = R(re[i][j]);
+        }
+}
+
 }  // namespace
 
 // Device resources of the planner, owned by a state handle.
@@ -368,33 +467,11 @@ static PlanCache *cache_of(sv_state s)
     return static_cast<PlanCache *>(s->plan);
 }
 
-sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
-                   std::string *err)
+// Copies `bytes` of host data to the handle's device plan buffer through a
+// pinned staging buffer, in stream order. Returns the device address.
+static sv_status stage_upload(sv_state s, size_t bytes, const std::function<void(char *)> &fill,
+                              char **dev_out, std::string *err)
 {
-    if (flags & (SV_FUSE_DENSE | SV_GRAPH)) {
-        *err = "SV_FUSE_DENSE and SV_GRAPH are not built yet";
-        return SV_EUNSUPPORTED;
-    }
-    const TileGeom geo = geometry(s->n, s->dt);
-    std::vector<Item> items;
-    items.reserve(n_gates);
-    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
-    bool ok = true;
-    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
-    if (!ok) {
-        *err = "planner could not place every gate with this tile geometry";
-        return SV_EUNSUPPORTED;
-    }
-    Flat f = flatten(s->n, geo, passes);
-
-    const bool c64 = s->dt == SV_C64;
-    const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
-    const size_t off_groups = 0;
-    const size_t off_ops = align_up(off_groups + f.groups.size() * sizeof(TileGroup), 256);
-    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
-    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
-    const size_t total = align_up(off_tab + tab_bytes, 256);
-
     PlanCache *pc = cache_of(s);
     hipError_t e = hipSuccess;
     if (pc->staged) {
@@ -404,6 +481,7 @@ sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t fl
         *err = hipGetErrorString(e);
         return SV_EDEVICE;
     }
+    const size_t total = align_up(bytes, 256);
     if (pc->host_cap < total) {
         if (pc->host) (void)hipHostFree(pc->host);
         pc->host = nullptr;
@@ -425,17 +503,45 @@ sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t fl
         }
         pc->dev_cap = total;
     }
-    char *h = static_cast<char *>(pc->host);
-    std::memcpy(h + off_groups, f.groups.data(), f.groups.size() * sizeof(TileGroup));
-    std::memcpy(h + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
-    std::memcpy(h + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
-    if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + off_tab));
-    else fill_phase_table(reinterpret_cast<double2 *>(h + off_tab));
+    fill(static_cast<char *>(pc->host));
     e = hipMemcpyAsync(pc->dev, pc->host, total, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipEventRecord(pc->staged, s->stream);
     if (e != hipSuccess) { *err = hipGetErrorString(e); return SV_EDEVICE; }
+    *dev_out = static_cast<char *>(pc->dev);
+    return SV_OK;
+}
 
-    char *d = static_cast<char *>(pc->dev);
+static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, std::string *err)
+{
+    const TileGeom geo = geometry(s->n, s->dt);
+    std::vector<Item> items;
+    items.reserve(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
+    bool ok = true;
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
+    if (!ok) {
+        *err = "planner could not place every gate with this tile geometry";
+        return SV_EUNSUPPORTED;
+    }
+    Flat f = flatten(s->n, geo, passes);
+
+    const bool c64 = s->dt == SV_C64;
+    const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
+    const size_t off_groups = 0;
+    const size_t off_ops = align_up(off_groups + f.groups.size() * sizeof(TileGroup), 256);
+    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
+    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
+    const size_t total = off_tab + tab_bytes;
+    char *d = nullptr;
+    sv_status st = stage_upload(s, total, [&](char *h) {
+        std::memcpy(h + off_groups, f.groups.data(), f.groups.size() * sizeof(TileGroup));
+        std::memcpy(h + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
+        std::memcpy(h + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
+        if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + off_tab));
+        else fill_phase_table(reinterpret_cast<double2 *>(h + off_tab));
+    }, &d, err);
+    if (st != SV_OK) return st;
+
     const double bytes = 2.0 * std::ldexp(1.0, s->n) * elem_bytes(s->dt);
     for (size_t p = 0; p < f.args.size(); ++p) {
         TileArgs a = f.args[p];
@@ -445,11 +551,54 @@ sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t fl
         a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
         a.phase_tab = d + off_tab;
         const int tok = prof_begin(s);
-        e = launch_tile(a, geo.K, c64, geo.prefetch, s->stream);
+        hipError_t e = launch_tile(a, geo.K, c64, geo.prefetch, s->stream);
         prof_end(s, tok, KC_TILE, bytes, f.flops[p]);
         if (e != hipSuccess) { *err = std::string("tile launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
     }
     return SV_OK;
+}
+
+static sv_status run_dense(sv_state s, const sv_gate *gates, size_t n_gates, std::string *err)
+{
+    const std::vector<DBlock> blocks = plan_dense(s->n, gates, n_gates);
+    const bool c64 = s->dt == SV_C64;
+    const size_t mat_bytes = 64 * 64 * (c64 ? sizeof(float) : sizeof(double));
+    char *d = nullptr;
+    sv_status st = stage_upload(s, blocks.size() * mat_bytes, [&](char *h) {
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            if (c64) block_matrix(blocks[b], gates, reinterpret_cast<float *>(h + b * mat_bytes));
+            else block_matrix(blocks[b], gates, reinterpret_cast<double *>(h + b * mat_bytes));
+        }
+    }, &d, err);
+    if (st != SV_OK) return st;
+    const uint64_t all = (uint64_t(1) << s->n) - 1;
+    const double N = std::ldexp(1.0, s->n);
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        DenseArgs a{};
+        a.psi = s->psi;
+        a.mat = d + b * mat_bytes;
+        a.bmask = blocks[b].qmask;
+        a.omask = all & ~blocks[b].qmask;
+        a.ncols = uint64_t(1) << (s->n - 5);
+        const int tok = prof_begin(s);
+        hipError_t e = launch_dense5(a, c64, s->stream);
+        prof_end(s, tok, KC_DENSE, 2.0 * N * elem_bytes(s->dt), 256.0 * N);
+        if (e != hipSuccess) { *err = std::string("dense launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
+    }
+    return SV_OK;
+}
+
+sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
+                   std::string *err)
+{
+    if (flags & SV_GRAPH) {
+        *err = "SV_GRAPH is not built yet";
+        return SV_EUNSUPPORTED;
+    }
+    // Dense blocks need at least 16 columns of 32 amplitudes (n >= 9); smaller
+    // registers are fused into tiles instead.
+    if ((flags & SV_FUSE_DENSE) && s->n >= 9) return run_dense(s, gates, n_gates, err);
+    return run_tiles(s, gates, n_gates, err);
 }
 
 void plan_release(sv_state s)
@@ -462,6 +611,27 @@ void plan_release(sv_state s)
     if (pc->staged) (void)hipEventDestroy(pc->staged);
     delete pc;
     s->plan = nullptr;
+}
+
+// Host-only view of a dense-block plan: block qubit masks and each block's
+// 32x32 complex matrix (row major, interleaved re/im) for the first `cap`
+// blocks; returns the number of blocks.
+int plan_dense_inspect(int n, const sv_gate *gates, size_t n_gates, uint64_t *masks,
+                       double *mats, int cap)
+{
+    const std::vector<DBlock> blocks = plan_dense(n, gates, n_gates);
+    std::vector<double> real(64 * 64);
+    for (int b = 0; b < int(blocks.size()) && b < cap; ++b) {
+        if (masks) masks[b] = blocks[b].qmask;
+        if (!mats) continue;
+        block_matrix(blocks[b], gates, real.data());
+        for (int i = 0; i < 32; ++i)
+            for (int j = 0; j < 32; ++j) {
+                mats[(size_t(b) * 1024 + i * 32 + j) * 2] = real[i * 64 + j];
+                mats[(size_t(b) * 1024 + i * 32 + j) * 2 + 1] = real[(32 + i) * 64 + j];
+            }
+    }
+    return int(blocks.size());
 }
 
 // Host-only view of a plan, for inspection and tests.

@@ -436,6 +436,22 @@ sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, si
     return SV_OK;
 }
 
+sv_status sv_plan_dense_inspect(int n_qubits, const sv_gate *gates, size_t n_gates,
+                                uint64_t *block_masks, double *block_mats, int32_t cap,
+                                int32_t *n_blocks)
+{
+    if (n_qubits < 5 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [5, 34]", n_qubits);
+    if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
+    if (cap < 0) return fail(SV_EINVAL, "negative capacity");
+    sv_state_s probe;
+    probe.n = n_qubits;
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
+    const int nb = svk::plan_dense_inspect(n_qubits, gates, n_gates, block_masks, block_mats, cap);
+    if (n_blocks) *n_blocks = nb;
+    return SV_OK;
+}
+
 sv_status sv_synchronize(sv_state s)
 {
     if (sv_status st = check_handle(s)) return st;
