@@ -165,6 +165,48 @@ sv_status sv_copy_in(sv_state s, const void *host_src);
 /* Waits for the handle's stream; SV_EDEVICE if queued work failed. */
 sv_status sv_synchronize(sv_state s);
 
+/* ---- planned circuits and batched launches --------------------------------
+ * A plan is a circuit fused into tile passes (as SV_FUSE does) and uploaded to
+ * the device once; it stays bound to the state it was made for. A batch runs
+ * pass ranges of many plans, on distinct states of one dtype, level by level:
+ * launch k applies pass k of every circuit that has one, all their tiles at
+ * once, so independent circuits overlap on the device and the launch boundary
+ * orders a circuit's passes. */
+typedef struct sv_plan_s *sv_plan;
+typedef struct sv_batch_s *sv_batch;
+
+/* Plans gates for state s (n >= 4) and uploads the plan (synchronous). The
+ * gate array is read during the call only. */
+sv_status sv_plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out);
+/* Frees the plan's device memory (waits for work that may use it). */
+sv_status sv_plan_destroy(sv_plan p);
+/* Number of passes (sweeps over the state) of the plan. */
+sv_status sv_plan_passes(sv_plan p, int32_t *n_passes);
+/* Queues passes [first_pass, first_pass + count) of the plan on its state's
+ * stream, one kernel launch per pass. */
+sv_status sv_run_plan(sv_plan p, int32_t first_pass, int32_t count);
+
+/* A batch workspace for dtype on hip_stream (NULL: null stream). A batch must
+ * not run twice at the same time; distinct batches may. */
+sv_status sv_batch_create(sv_dtype dtype, void *hip_stream, sv_batch *out);
+sv_status sv_batch_destroy(sv_batch b);
+/* Tuning: work-groups per CU of each level launch (1..8, default 2) and tiles
+ * per task (1..4096, default 8). */
+sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task);
+/* Queues passes [first_pass[i], first_pass[i] + pass_count[i]) of plans[i],
+ * i < count, on the batch's stream (first_pass NULL: from 0; pass_count NULL:
+ * to the end). The plans' states must be distinct and of the batch's dtype;
+ * their own streams are not used, so the caller orders the batch stream after
+ * earlier work on those states. flags: 0 or SV_GRAPH (the level launches are
+ * captured in a HIP graph once per identical request and replayed). */
+sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pass,
+                       const int32_t *pass_count, size_t count, uint32_t flags);
+/* Waits for the batch stream and writes, for each circuit of the last run,
+ * the device-clock times (ms) at which its first tile task started and its
+ * last one ended, relative to the earliest start (0 for a circuit with no
+ * passes in the run). count must equal that run's. */
+sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t count);
+
 /* Plans a gate list for SV_FUSE on the host only (no device is touched) and
  * reports its shape: *n_passes sweeps over the state, *n_groups register
  * groups, *n_ops ops in execution order; gate_op[i] (n_gates entries, or

@@ -22,7 +22,9 @@ __all__ = [
     "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
-    "sv_plan_inspect", "sv_plan_dense_inspect", "StateVector", "LIB_PATH",
+    "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
+    "sv_plan_passes", "sv_run_plan", "sv_batch_create", "sv_batch_destroy", "sv_batch_config",
+    "sv_batch_run", "sv_batch_times", "StateVector", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsv.so")
@@ -85,6 +87,15 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _int),
     "sv_plan_dense_inspect": ([_int, _vp, _sz, _vp, _vp, ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_int32)], _int),
+    "sv_plan_create": ([_vp, _vp, _sz, ctypes.POINTER(_vp)], _int),
+    "sv_plan_destroy": ([_vp], _int),
+    "sv_plan_passes": ([_vp, ctypes.POINTER(ctypes.c_int32)], _int),
+    "sv_run_plan": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
+    "sv_batch_create": ([_int, _vp, ctypes.POINTER(_vp)], _int),
+    "sv_batch_destroy": ([_vp], _int),
+    "sv_batch_config": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
+    "sv_batch_run": ([_vp, _vp, _vp, _vp, _sz, _u32], _int),
+    "sv_batch_times": ([_vp, _dp, _dp, _sz], _int),
     "sv_profile_read": ([_vp, ctypes.POINTER(_ProfEntry), _int, ctypes.POINTER(_int)], _int),
 }
 
@@ -263,6 +274,65 @@ def sv_plan_dense_inspect(n_qubits: int, gates: np.ndarray, cap: int | None = No
     _check(lib().sv_plan_dense_inspect(n_qubits, ptr, len(g), masks.ctypes.data, mats.ctypes.data,
                                        cap, ctypes.byref(nb)))
     return masks, mats
+
+
+def _gates(gates):
+    g = np.ascontiguousarray(gates)
+    if g.dtype != GATE_DTYPE:
+        g = g.astype(GATE_DTYPE)
+    return g
+
+
+def sv_plan_create(h: int, gates: np.ndarray) -> int:
+    g = _gates(gates)
+    p = _vp()
+    _check(lib().sv_plan_create(h, g.ctypes.data if len(g) else None, len(g), ctypes.byref(p)))
+    return p.value
+
+
+def sv_plan_destroy(p: int) -> None:
+    _check(lib().sv_plan_destroy(p))
+
+
+def sv_plan_passes(p: int) -> int:
+    v = ctypes.c_int32()
+    _check(lib().sv_plan_passes(p, ctypes.byref(v)))
+    return v.value
+
+
+def sv_run_plan(p: int, first_pass: int, count: int) -> None:
+    _check(lib().sv_run_plan(p, first_pass, count))
+
+
+def sv_batch_create(dtype: int, stream: int | None = None) -> int:
+    b = _vp()
+    _check(lib().sv_batch_create(dtype, stream, ctypes.byref(b)))
+    return b.value
+
+
+def sv_batch_destroy(b: int) -> None:
+    _check(lib().sv_batch_destroy(b))
+
+
+def sv_batch_config(b: int, blocks_per_cu: int, tiles_per_task: int) -> None:
+    _check(lib().sv_batch_config(b, blocks_per_cu, tiles_per_task))
+
+
+def sv_batch_run(b: int, plans, first_pass=None, pass_count=None, flags: int = 0) -> None:
+    n = len(plans)
+    arr = (_vp * max(n, 1))(*plans)
+    fp = None if first_pass is None else np.ascontiguousarray(first_pass, dtype=np.int32)
+    pc = None if pass_count is None else np.ascontiguousarray(pass_count, dtype=np.int32)
+    _check(lib().sv_batch_run(b, arr, None if fp is None else fp.ctypes.data,
+                              None if pc is None else pc.ctypes.data, n, flags))
+
+
+def sv_batch_times(b: int, count: int):
+    """(start_ms, end_ms) per circuit of the last run (device clock, waits)."""
+    st = np.zeros(count)
+    en = np.zeros(count)
+    _check(lib().sv_batch_times(b, st.ctypes.data_as(_dp), en.ctypes.data_as(_dp), count))
+    return st, en
 
 
 class StateVector:

@@ -34,7 +34,7 @@ typedef double dv2 __attribute__((ext_vector_type(2)));
 
 // Plan data is read through the constant address space: the loads are
 // uniform, become scalar (s_load), and never wait on the vector-memory
-// counter that tracks the prefetch of the next tile.
+// counter that tracks the tile loads.
 #define SV_CONST __attribute__((address_space(4)))
 typedef const SV_CONST TileGroup CGroup;
 typedef const SV_CONST TileOp COp;
@@ -194,107 +194,138 @@ __device__ __forceinline__ void apply_diag(AmpT<C64> (&v)[1 << K], const uint32_
         if (T[r] != 0) v[r] = cmul(v[r], turn_phase<C64>(T[r], tab));
 }
 
-// One work-group walks tiles blockIdx.x, +gridDim.x, ...; the next tile's
-// amplitudes are loaded into registers while the current one is processed.
-template <bool C64, int K, bool PREF>
-__device__ __forceinline__ void tile_body(const TileArgs a)
+// Processes tiles g = g0, g0 + gstep, ... below gend of the pass `a` with one
+// work-group. Threads tid >= 2^(L-K) (a tile smaller than the work-group) take
+// part in the barriers only.
+template <bool C64, int K>
+__device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
+                                          uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab)
 {
     using A = AmpT<C64>;
     constexpr int NR = 1 << K;
-    extern __shared__ __align__(16) unsigned char smem[];
-    A *lds = reinterpret_cast<A *>(smem);
-    const uint32_t size = 1u << a.L;
-    const uint32_t slots = C64 ? size + (size >> 5) : size + (size >> 4);
-    A *tab = lds + slots;
     const uint32_t W = 1u << (a.L - K);
     const uint32_t tid = threadIdx.x;
+    const bool active = tid < W;
     A *psi = static_cast<A *>(a.psi);
-
-    if (a.has_diag) {
-        const A *src = static_cast<const A *>(a.phase_tab);
-        for (uint32_t i = tid; i < 512; i += W) tab[i] = src[i];
-    }
     CGroup *groups = (CGroup *)(a.groups);
     COp *ops = (COp *)(a.ops);
     CPivot *pivots = (CPivot *)(a.pivots);
+
+    if (a.has_diag) {
+        const A *src = static_cast<const A *>(a.phase_tab);
+        for (uint32_t i = tid; i < 512; i += blockDim.x) tab[i] = src[i];
+    }
     const uint64_t dt = deposit(tid, a.tmask);
     uint64_t roff[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) roff[r] = deposit(uint64_t(r) * W, a.tmask);
 
-    uint64_t g = blockIdx.x;
-    A pv[NR];
-    if (PREF && g < a.ntiles) {
-        const uint64_t gb = deposit(g, a.omask) | dt;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) pv[r] = psi[gb | roff[r]];
-    }
-    while (g < a.ntiles) {
+    for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
-        if (!PREF) {
+        if (active) {
+            A pv[NR];
 #pragma unroll
             for (int r = 0; r < NR; ++r) pv[r] = psi[gbase | dt | roff[r]];
-        }
 #pragma unroll
-        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tid + uint32_t(r) * W)] = pv[r];
+            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tid + uint32_t(r) * W)] = pv[r];
+        }
         __syncthreads();
-        const uint64_t gn = g + gridDim.x;
-        if (PREF && gn < a.ntiles) {
-            const uint64_t gb = deposit(gn, a.omask) | dt;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) pv[r] = psi[gb | roff[r]];
-        }
         for (int gi = 0; gi < a.ngroups; ++gi) {
             CGroup &G = groups[a.group0 + gi];
-            uint32_t lbase = 0;
-            for (int k = 0; k < a.L - K; ++k) lbase |= ((tid >> k) & 1u) << G.ns[k];
-            uint32_t soff[K];
+            if (active) {
+                uint32_t lbase = 0;
+                for (int k = 0; k < a.L - K; ++k) lbase |= ((tid >> k) & 1u) << G.ns[k];
+                uint32_t soff[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) soff[k] = 1u << G.s[k];
-            uint32_t li[NR];
-            A v[NR];
+                for (int k = 0; k < K; ++k) soff[k] = 1u << G.s[k];
+                uint32_t li[NR];
+                A v[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                uint32_t l = lbase;
+                for (int r = 0; r < NR; ++r) {
+                    uint32_t l = lbase;
 #pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (r & (1 << k)) l |= soff[k];
-                li[r] = l;
-                v[r] = lds[lds_slot<C64>(l)];
-            }
-            for (int oi = 0; oi < G.nops; ++oi) {
-                COp &op = ops[G.op0 + oi];
-                if (op.kind == TOP_DIAG) {
-                    apply_diag<C64, K>(v, li, op, pivots, a.L, G, gbase, tid, tab);
-                    continue;
+                    for (int k = 0; k < K; ++k)
+                        if (r & (1 << k)) l |= soff[k];
+                    li[r] = l;
+                    v[r] = lds[lds_slot<C64>(l)];
                 }
-                if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) continue;
-                const bool ctrl = op.lctrl >= 0;
-                if (op.kind == TOP_SWAP) {
-                    if (ctrl) apply_pair<C64, K, true, true>(v, li, op);
-                    else apply_pair<C64, K, true, false>(v, li, op);
-                } else {
-                    if (ctrl) apply_pair<C64, K, false, true>(v, li, op);
-                    else apply_pair<C64, K, false, false>(v, li, op);
+                for (int oi = 0; oi < G.nops; ++oi) {
+                    COp &op = ops[G.op0 + oi];
+                    if (op.kind == TOP_DIAG) {
+                        apply_diag<C64, K>(v, li, op, pivots, a.L, G, gbase, tid, tab);
+                        continue;
+                    }
+                    if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) continue;
+                    const bool ctrl = op.lctrl >= 0;
+                    if (op.kind == TOP_SWAP) {
+                        if (ctrl) apply_pair<C64, K, true, true>(v, li, op);
+                        else apply_pair<C64, K, true, false>(v, li, op);
+                    } else {
+                        if (ctrl) apply_pair<C64, K, false, true>(v, li, op);
+                        else apply_pair<C64, K, false, false>(v, li, op);
+                    }
                 }
-            }
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+                for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+            }
             __syncthreads();
         }
         // Each thread stores the slots it filled, so the next fill needs no barrier.
-        const uint64_t gb = gbase | dt;
+        if (active) {
+            const uint64_t gb = gbase | dt;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(tid + uint32_t(r) * W)];
-        g = gn;
+            for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(tid + uint32_t(r) * W)];
+        }
     }
 }
 
-// One kernel per (dtype, register bits K, prefetch) with at most MAXT threads.
-template <bool C64, int K, bool PREF, int MAXT>
+template <bool C64>
+__device__ __forceinline__ AmpT<C64> *lds_base()
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    return reinterpret_cast<AmpT<C64> *>(smem);
+}
+
+// One pass: work-group blockIdx.x walks tiles blockIdx.x, +gridDim.x, ...
+template <bool C64, int K, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_tile(TileArgs a)
 {
-    tile_body<C64, K, PREF>(a);
+    using A = AmpT<C64>;
+    A *lds = lds_base<C64>();
+    const uint32_t size = 1u << a.L;
+    A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+    run_tiles<C64, K>(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab);
+}
+
+// One pass level of a batch: every task (a chunk of tiles of one pass of one
+// circuit) of the level is independent of the others, so work-groups take
+// tasks blockIdx.x, +gridDim.x, ... with no waiting; the launch boundary
+// orders consecutive levels of a circuit. Each task stores its start and end
+// device clock.
+template <bool C64, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
+{
+    using A = AmpT<C64>;
+    constexpr int K = 4;
+    A *lds = lds_base<C64>();
+    const BatchTask SV_CONST *tasks = (const BatchTask SV_CONST *)(b.tasks);
+    const TileArgs SV_CONST *passes = (const TileArgs SV_CONST *)(b.passes);
+    for (uint32_t ti = b.task0 + blockIdx.x; ti < b.task_end; ti += gridDim.x) {
+        const BatchTask SV_CONST &t = tasks[ti];
+        const uint32_t tile0 = t.tile0, ntiles = t.ntiles;
+        const TileArgs SV_CONST &pc = passes[t.pass];
+        TileArgs a;
+        a.psi = pc.psi; a.groups = pc.groups; a.ops = pc.ops; a.pivots = pc.pivots;
+        a.phase_tab = pc.phase_tab; a.tmask = pc.tmask; a.omask = pc.omask; a.ntiles = pc.ntiles;
+        a.L = pc.L; a.nlow = pc.nlow; a.nnon = pc.nnon; a.group0 = pc.group0;
+        a.ngroups = pc.ngroups; a.has_diag = pc.has_diag;
+        if (threadIdx.x == 0) b.t_start[ti] = wall_clock64();
+        const uint32_t size = 1u << a.L;
+        A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+        run_tiles<C64, K>(a, tile0, uint64_t(tile0) + ntiles, 1, lds, tab);
+        if (threadIdx.x == 0) b.t_end[ti] = wall_clock64();
+        __syncthreads();   // the next task reuses LDS
+    }
 }
 
 int cu_count()
@@ -311,12 +342,18 @@ int cu_count()
 }
 
 template <typename Kern>
-hipError_t launch_k(Kern kern, bool c64, const TileArgs &a, int K, size_t lds, hipStream_t st)
+hipError_t set_max_lds(Kern kern, bool c64)
 {
     // Allow the largest tile this dtype uses (above the 64 KiB default).
     const int max_lds = int(tile_lds_bytes(c64, c64 ? kTileL64 : kTileL128, true));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+template <typename Kern>
+hipError_t launch_k(Kern kern, bool c64, const TileArgs &a, int K, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_max_lds(kern, c64);
     if (e != hipSuccess) return e;
     const uint64_t want = uint64_t(cu_count()) * 2;
     const unsigned grid = unsigned(a.ntiles < want ? a.ntiles : want);
@@ -324,26 +361,44 @@ hipError_t launch_k(Kern kern, bool c64, const TileArgs &a, int K, size_t lds, h
     return hipGetLastError();
 }
 
-template <bool C64, bool PREF>
+template <bool C64>
 hipError_t launch_dt(const TileArgs &a, int K, size_t lds, hipStream_t st)
 {
     switch (K) {
-    case 1: return launch_k(k_tile<C64, 1, PREF, 1024>, C64, a, K, lds, st);
-    case 2: return launch_k(k_tile<C64, 2, PREF, 1024>, C64, a, K, lds, st);
-    case 3: return launch_k(k_tile<C64, 3, PREF, C64 ? 1024 : 512>, C64, a, K, lds, st);
-    case 4: return launch_k(k_tile<C64, 4, PREF, C64 ? 512 : 256>, C64, a, K, lds, st);
+    case 1: return launch_k(k_tile<C64, 1, 1024>, C64, a, K, lds, st);
+    case 2: return launch_k(k_tile<C64, 2, 1024>, C64, a, K, lds, st);
+    case 3: return launch_k(k_tile<C64, 3, C64 ? 1024 : 512>, C64, a, K, lds, st);
+    case 4: return launch_k(k_tile<C64, 4, C64 ? 512 : 256>, C64, a, K, lds, st);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_tile(const TileArgs &a, int K, bool c64, bool prefetch, hipStream_t st)
+hipError_t launch_tile(const TileArgs &a, int K, bool c64, hipStream_t st)
 {
     if ((1u << (a.L - K)) > 1024u) return hipErrorInvalidValue;
     const size_t lds = tile_lds_bytes(c64, a.L, a.has_diag != 0);
-    if (c64) return prefetch ? launch_dt<true, true>(a, K, lds, st) : launch_dt<true, false>(a, K, lds, st);
-    return prefetch ? launch_dt<false, true>(a, K, lds, st) : launch_dt<false, false>(a, K, lds, st);
+    return c64 ? launch_dt<true>(a, K, lds, st) : launch_dt<false>(a, K, lds, st);
+}
+
+hipError_t launch_level(const BatchArgs &b, bool c64, int blocks_per_cu, hipStream_t st)
+{
+    const uint32_t ntasks = b.task_end - b.task0;
+    if (ntasks == 0) return hipSuccess;
+    const int threads = c64 ? (1 << (kTileL64 - 4)) : (1 << (kTileL128 - 4));
+    const size_t lds = tile_lds_bytes(c64, c64 ? kTileL64 : kTileL128, true);
+    const uint32_t want = uint32_t(cu_count() * (blocks_per_cu > 0 ? blocks_per_cu : 2));
+    const unsigned grid = ntasks < want ? ntasks : want;
+    hipError_t e;
+    if (c64) {
+        if ((e = set_max_lds(k_level<true, 512>, true)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_level<true, 512>), dim3(grid), dim3(threads), lds, st, b);
+    } else {
+        if ((e = set_max_lds(k_level<false, 256>, false)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_level<false, 256>), dim3(grid), dim3(threads), lds, st, b);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace svk

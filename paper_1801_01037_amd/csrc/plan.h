@@ -17,6 +17,11 @@ void plan_release(sv_state s);
 
 // Plans without a device: gate_op[i] (n_gates entries, may be NULL) receives
 // the index, in execution order, of the last op that carries gate i.
+// Plans a validated gate list into tile passes (K = 4 geometry) and uploads
+// them; the plan object is owned by the caller (sv_plan_destroy).
+sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out,
+                      std::string *err);
+
 int plan_dense_inspect(int n, const sv_gate *gates, size_t n_gates, uint64_t *masks,
                        double *mats, int cap);
 int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32_t *gate_op,

@@ -75,22 +75,20 @@ struct PPass {
 
 struct TileGeom {
     int L, K, nlow;
-    bool prefetch;
 };
 
-TileGeom geometry(int n, sv_dtype dt)
+TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
 {
     const bool c64 = dt == SV_C64;
     TileGeom g;
     int L = c64 ? kTileL64 : kTileL128;
     int K = c64 ? kTileK64 : kTileK128;
     int nlow = c64 ? 6 : 5;
-    g.prefetch = false;   // measured faster: the prefetch registers cost occupancy
     // Tuning overrides (bounded to what the kernels are built for).
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
     if (const char *e = std::getenv("SV_TILE_NLOW")) nlow = std::atoi(e);
-    if (const char *e = std::getenv("SV_TILE_PREFETCH")) g.prefetch = std::atoi(e) != 0;
+    if (force_k > 0) K = force_k;
     g.L = std::min(n, L);
     g.K = std::min(g.L, K);
     if (g.L - g.K > 10) g.K = g.L - 10;   // at most 1024 threads
@@ -551,7 +549,7 @@ static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, std
         a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
         a.phase_tab = d + off_tab;
         const int tok = prof_begin(s);
-        hipError_t e = launch_tile(a, geo.K, c64, geo.prefetch, s->stream);
+        hipError_t e = launch_tile(a, geo.K, c64, s->stream);
         prof_end(s, tok, KC_TILE, bytes, f.flops[p]);
         if (e != hipSuccess) { *err = std::string("tile launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
     }
@@ -664,3 +662,410 @@ int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32
 }
 
 }  // namespace svk
+
+// ---- planned circuits and batched launches -----------------------------------
+
+namespace svk {
+namespace {
+
+}  // namespace
+}  // namespace svk
+
+namespace svk {
+
+int wall_clock_khz()
+{
+    static int khz = 0;
+    if (khz == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+    }
+    return khz;
+}
+
+}  // namespace svk
+
+struct sv_plan_s {
+    sv_state st = nullptr;
+    int n = 0;
+    sv_dtype dt = SV_C128;
+    std::vector<svk::TileArgs> passes;   // device pointers patched
+    std::vector<double> flops;
+    void *dev = nullptr;
+};
+
+// Device buffers of one prepared batch: tasks | passes | start clocks | end clocks.
+struct BatchImage {
+    void *dev = nullptr;
+    size_t cap = 0;
+    size_t off_pass = 0, off_start = 0, off_end = 0;
+    std::vector<uint32_t> level0;      // first task of each level, plus the end
+    std::vector<int32_t> task_circ;    // circuit of each task
+    size_t count = 0;                  // circuits
+};
+
+struct sv_batch_s {
+    sv_dtype dt = SV_C64;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;     // private stream for graph capture
+    int blocks_per_cu = 2;
+    uint32_t tiles_per_task = 8;
+    BatchImage work;                   // runs without SV_GRAPH
+    BatchImage gimg;                   // the captured graph's own buffers
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uintptr_t> gkey;       // content the graph was captured for
+    void *host = nullptr;              // pinned staging
+    size_t host_cap = 0;
+    hipEvent_t staged = nullptr;
+    const BatchImage *last = nullptr;  // image of the last run (for sv_batch_times)
+};
+
+namespace {
+
+sv_status berr(sv_status st, const std::string &m) { return svk::set_error(st, m); }
+
+}  // namespace
+
+namespace svk {
+
+sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out, std::string *err)
+{
+    if (s->n < 4) {
+        *err = "planned circuits need at least 4 qubits";
+        return SV_EINVAL;
+    }
+    const TileGeom geo = geometry(s->n, s->dt, 4);
+    std::vector<Item> items;
+    items.reserve(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
+    bool ok = true;
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
+    if (!ok) {
+        *err = "planner could not place every gate with this tile geometry";
+        return SV_EUNSUPPORTED;
+    }
+    Flat f = flatten(s->n, geo, passes);
+    const bool c64 = s->dt == SV_C64;
+    const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
+    const size_t off_ops = align_up(f.groups.size() * sizeof(TileGroup), 256);
+    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
+    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
+    const size_t total = off_tab + tab_bytes;
+    std::vector<char> h(total);
+    std::memcpy(h.data(), f.groups.data(), f.groups.size() * sizeof(TileGroup));
+    std::memcpy(h.data() + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
+    std::memcpy(h.data() + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
+    if (c64) fill_phase_table(reinterpret_cast<float2 *>(h.data() + off_tab));
+    else fill_phase_table(reinterpret_cast<double2 *>(h.data() + off_tab));
+    sv_plan p = new (std::nothrow) sv_plan_s;
+    if (!p) { *err = "host allocation failed"; return SV_ENOMEM; }
+    hipError_t e = hipMalloc(&p->dev, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        *err = "device allocation of the plan failed";
+        return SV_ENOMEM;
+    }
+    // Synchronous upload: plans are built once, outside the hot loop.
+    e = hipMemcpy(p->dev, h.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev);
+        delete p;
+        *err = hipGetErrorString(e);
+        return SV_EDEVICE;
+    }
+    char *d = static_cast<char *>(p->dev);
+    for (TileArgs a : f.args) {
+        a.psi = s->psi;
+        a.groups = reinterpret_cast<const TileGroup *>(d);
+        a.ops = reinterpret_cast<const TileOp *>(d + off_ops);
+        a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
+        a.phase_tab = d + off_tab;
+        p->passes.push_back(a);
+    }
+    p->flops = f.flops;
+    p->st = s;
+    p->n = s->n;
+    p->dt = s->dt;
+    *out = p;
+    return SV_OK;
+}
+
+}  // namespace svk
+
+extern "C" {
+
+sv_status sv_plan_destroy(sv_plan p)
+{
+    if (!p) return SV_OK;
+    if (p->dev) (void)hipFree(p->dev);   // waits for work that may still read it
+    delete p;
+    return SV_OK;
+}
+
+sv_status sv_plan_passes(sv_plan p, int32_t *n_passes)
+{
+    if (!p || !n_passes) return berr(SV_EINVAL, "null argument");
+    *n_passes = int32_t(p->passes.size());
+    return SV_OK;
+}
+
+sv_status sv_run_plan(sv_plan p, int32_t first_pass, int32_t count)
+{
+    if (!p) return berr(SV_EINVAL, "null plan");
+    if (first_pass < 0 || count < 0 || size_t(first_pass) + size_t(count) > p->passes.size())
+        return berr(SV_EINVAL, "pass range outside the plan");
+    sv_state s = p->st;
+    const double bytes = 2.0 * std::ldexp(1.0, s->n) * svk::elem_bytes(s->dt);
+    for (int32_t i = first_pass; i < first_pass + count; ++i) {
+        const int tok = svk::prof_begin(s);
+        hipError_t e = svk::launch_tile(p->passes[i], 4, s->dt == SV_C64, s->stream);
+        svk::prof_end(s, tok, svk::KC_TILE, bytes, p->flops[i]);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("tile launch: ") + hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+sv_status sv_batch_create(sv_dtype dtype, void *hip_stream, sv_batch *out)
+{
+    if (!out) return berr(SV_EINVAL, "null output pointer");
+    if (dtype != SV_C64 && dtype != SV_C128) return berr(SV_EINVAL, "unknown dtype");
+    sv_batch b = new (std::nothrow) sv_batch_s;
+    if (!b) return berr(SV_ENOMEM, "host allocation failed");
+    b->dt = dtype;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return berr(SV_EDEVICE, "event creation failed");
+    }
+    *out = b;
+    return SV_OK;
+}
+
+sv_status sv_batch_destroy(sv_batch b)
+{
+    if (!b) return SV_OK;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->work.dev) (void)hipFree(b->work.dev);
+    if (b->gimg.dev) (void)hipFree(b->gimg.dev);
+    if (b->host) (void)hipHostFree(b->host);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+    return SV_OK;
+}
+
+sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task)
+{
+    if (!b) return berr(SV_EINVAL, "null batch");
+    if (blocks_per_cu < 1 || blocks_per_cu > 8) return berr(SV_EINVAL, "blocks_per_cu not in [1, 8]");
+    if (tiles_per_task < 1 || tiles_per_task > 4096) return berr(SV_EINVAL, "tiles_per_task not in [1, 4096]");
+    if (b->blocks_per_cu != blocks_per_cu || b->tiles_per_task != uint32_t(tiles_per_task)) {
+        b->blocks_per_cu = blocks_per_cu;
+        b->tiles_per_task = uint32_t(tiles_per_task);
+        b->gkey.clear();   // a captured graph used the old configuration
+    }
+    return SV_OK;
+}
+
+namespace {
+
+// Builds the level-ordered task list of a batch into `img` (device buffers
+// grown as needed) and queues its upload on `st` through pinned staging.
+sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
+                        const std::vector<int32_t> &first, const std::vector<int32_t> &cnt,
+                        hipStream_t st)
+{
+    using namespace svk;
+    const size_t count = first.size();
+    std::vector<TileArgs> passes;
+    std::vector<size_t> pass0(count);
+    for (size_t i = 0; i < count; ++i) {
+        pass0[i] = passes.size();
+        for (int32_t k = 0; k < cnt[i]; ++k) passes.push_back(plans[i]->passes[first[i] + k]);
+    }
+    std::vector<BatchTask> tasks;
+    img.level0.clear();
+    img.task_circ.clear();
+    int32_t maxc = 0;
+    for (size_t i = 0; i < count; ++i) maxc = std::max(maxc, cnt[i]);
+    for (int32_t lev = 0; lev < maxc; ++lev) {
+        img.level0.push_back(uint32_t(tasks.size()));
+        for (size_t i = 0; i < count; ++i) {
+            if (lev >= cnt[i]) continue;
+            const uint64_t nt = passes[pass0[i] + lev].ntiles;
+            for (uint64_t t0 = 0; t0 < nt; t0 += b->tiles_per_task) {
+                BatchTask t;
+                t.pass = int32_t(pass0[i] + lev);
+                t.circ = int32_t(i);
+                t.tile0 = uint32_t(t0);
+                t.ntiles = uint32_t(std::min<uint64_t>(b->tiles_per_task, nt - t0));
+                tasks.push_back(t);
+                img.task_circ.push_back(int32_t(i));
+            }
+        }
+    }
+    img.level0.push_back(uint32_t(tasks.size()));
+    img.count = count;
+    img.off_pass = align_up(tasks.size() * sizeof(BatchTask), 256);
+    img.off_start = align_up(img.off_pass + passes.size() * sizeof(TileArgs), 256);
+    img.off_end = align_up(img.off_start + tasks.size() * sizeof(uint64_t), 256);
+    const size_t total = align_up(img.off_end + tasks.size() * sizeof(uint64_t), 256);
+    const size_t upload = img.off_start;
+    hipError_t e = hipEventSynchronize(b->staged);   // staging free again
+    if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
+    if (b->host_cap < upload) {
+        if (b->host) (void)hipHostFree(b->host);
+        b->host = nullptr;
+        b->host_cap = 0;
+        if (hipHostMalloc(&b->host, upload, 0) != hipSuccess) return berr(SV_ENOMEM, "pinned staging failed");
+        b->host_cap = upload;
+    }
+    if (img.cap < total) {
+        if (img.dev) (void)hipFree(img.dev);   // waits for work that may use it
+        img.dev = nullptr;
+        img.cap = 0;
+        if (hipMalloc(&img.dev, total) != hipSuccess) {
+            (void)hipGetLastError();
+            return berr(SV_ENOMEM, "batch workspace allocation failed");
+        }
+        img.cap = total;
+    }
+    char *h = static_cast<char *>(b->host);
+    std::memcpy(h, tasks.data(), tasks.size() * sizeof(BatchTask));
+    std::memcpy(h + img.off_pass, passes.data(), passes.size() * sizeof(TileArgs));
+    e = hipMemcpyAsync(img.dev, h, upload, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(b->staged, st);
+    if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
+    return SV_OK;
+}
+
+// Queues one launch per level of `img` on `st`.
+sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
+{
+    using namespace svk;
+    char *d = static_cast<char *>(img.dev);
+    BatchArgs a{};
+    a.tasks = reinterpret_cast<const BatchTask *>(d);
+    a.passes = reinterpret_cast<const TileArgs *>(d + img.off_pass);
+    a.t_start = reinterpret_cast<uint64_t *>(d + img.off_start);
+    a.t_end = reinterpret_cast<uint64_t *>(d + img.off_end);
+    for (size_t lev = 0; lev + 1 < img.level0.size(); ++lev) {
+        a.task0 = img.level0[lev];
+        a.task_end = img.level0[lev + 1];
+        hipError_t e = launch_level(a, b->dt == SV_C64, b->blocks_per_cu, st);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("level launch: ") + hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pass,
+                       const int32_t *pass_count, size_t count, uint32_t flags)
+{
+    if (!b) return berr(SV_EINVAL, "null batch");
+    if (flags & ~SV_GRAPH) return berr(SV_EINVAL, "unknown batch flags");
+    if (count == 0) return SV_OK;
+    if (!plans) return berr(SV_EINVAL, "null plan array");
+    if (count > (1u << 20)) return berr(SV_EINVAL, "too many circuits in one batch");
+    std::vector<int32_t> first(count), cnt(count);
+    std::vector<uintptr_t> key;
+    key.reserve(3 * count + 2);
+    key.push_back(uintptr_t(b->blocks_per_cu));
+    key.push_back(uintptr_t(b->tiles_per_task));
+    for (size_t i = 0; i < count; ++i) {
+        const sv_plan p = plans[i];
+        if (!p) return berr(SV_EINVAL, "null plan in batch");
+        if (p->dt != b->dt) return berr(SV_EINVAL, "plan dtype differs from the batch dtype");
+        first[i] = first_pass ? first_pass[i] : 0;
+        cnt[i] = pass_count ? pass_count[i] : int32_t(p->passes.size()) - first[i];
+        if (first[i] < 0 || cnt[i] < 0 || size_t(first[i]) + size_t(cnt[i]) > p->passes.size())
+            return berr(SV_EINVAL, "pass range outside a plan");
+        for (size_t j = 0; j < i; ++j)
+            if (plans[j]->st == p->st) return berr(SV_EINVAL, "two plans of one state in a batch");
+        key.push_back(reinterpret_cast<uintptr_t>(p));
+        key.push_back(uintptr_t(first[i]));
+        key.push_back(uintptr_t(cnt[i]));
+    }
+    if (!(flags & SV_GRAPH)) {
+        if (sv_status st = prepare_batch(b, b->work, plans, first, cnt, b->stream)) return st;
+        if (sv_status st = launch_levels(b, b->work, b->stream)) return st;
+        b->last = &b->work;
+        return SV_OK;
+    }
+    // SV_GRAPH: capture the level launches once per content, then replay.
+    if (!b->gexec || b->gkey != key) {
+        if (b->gexec) {
+            (void)hipStreamSynchronize(b->stream);
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+        }
+        b->gkey.clear();
+        if (!b->capture && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
+            return berr(SV_EDEVICE, "capture stream creation failed");
+        if (sv_status st = prepare_batch(b, b->gimg, plans, first, cnt, b->capture)) return st;
+        hipError_t e = hipStreamSynchronize(b->capture);   // buffers uploaded before capture
+        if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
+        e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+        sv_status st = launch_levels(b, b->gimg, b->capture);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(b->capture, &graph);
+        if (st != SV_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("end capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            return berr(SV_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        b->gkey = key;
+    }
+    hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+    if (e != hipSuccess) return berr(SV_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    b->last = &b->gimg;
+    return SV_OK;
+}
+
+sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t count)
+{
+    if (!b) return berr(SV_EINVAL, "null batch");
+    const BatchImage *img = b->last;
+    if (!img || count != img->count) return berr(SV_EINVAL, "count differs from the last run");
+    const size_t nt = img->task_circ.size();
+    std::vector<uint64_t> t0(nt), t1(nt);
+    hipError_t e = hipSuccess;
+    if (nt) {
+        e = hipMemcpyAsync(t0.data(), static_cast<char *>(img->dev) + img->off_start,
+                           nt * sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t1.data(), static_cast<char *>(img->dev) + img->off_end,
+                               nt * sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
+    const int khz = svk::wall_clock_khz();
+    uint64_t origin = ~uint64_t(0);
+    for (size_t k = 0; k < nt; ++k) origin = std::min(origin, t0[k]);
+    std::vector<uint64_t> first(count, ~uint64_t(0)), last(count, 0);
+    for (size_t k = 0; k < nt; ++k) {
+        const int32_t c = img->task_circ[k];
+        first[c] = std::min(first[c], t0[k]);
+        last[c] = std::max(last[c], t1[k]);
+    }
+    for (size_t i = 0; i < count; ++i) {
+        const bool none = first[i] == ~uint64_t(0);   // no passes in the run
+        if (start_ms) start_ms[i] = none ? 0.0 : double(first[i] - origin) / khz;
+        if (end_ms) end_ms[i] = none ? 0.0 : double(last[i] - origin) / khz;
+    }
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -148,6 +148,12 @@ sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
 
 namespace svk {
 
+sv_status set_error(sv_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
 uint64_t angle_to_turn(double theta)
 {
     // theta / (2 pi) as a fraction of a turn in [0, 1), scaled by 2^64. For
@@ -449,6 +455,21 @@ sv_status sv_plan_dense_inspect(int n_qubits, const sv_gate *gates, size_t n_gat
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
     const int nb = svk::plan_dense_inspect(n_qubits, gates, n_gates, block_masks, block_mats, cap);
     if (n_blocks) *n_blocks = nb;
+    return SV_OK;
+}
+
+sv_status sv_plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!out) return fail(SV_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = validate_gate(s, gates[i], i)) return st;
+    DeviceScope ds(s->device);
+    std::string err;
+    sv_status st = svk::plan_create(s, gates, n_gates, out, &err);
+    if (st != SV_OK) return fail(st, "%s", err.c_str());
     return SV_OK;
 }
 

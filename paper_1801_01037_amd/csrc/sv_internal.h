@@ -52,6 +52,8 @@ hipError_t launch_probs(const void *psi, sv_dtype dt, uint64_t first, uint64_t c
                         double *out_dev, hipStream_t st);
 
 // ---- host helpers (sv_api.hip) ---------------------------------------------
+// Records `msg` as the calling thread's last error and returns `st`.
+sv_status set_error(sv_status st, const std::string &msg);
 uint64_t angle_to_turn(double theta);     // theta radians -> turns * 2^64 (mod 2^64)
 bool is_pauli_x(const double m[8]);
 bool is_phase_diag(const double m[8]);    // diag(1, e^{i phi}) with |e^{i phi}| == 1

@@ -81,7 +81,27 @@ struct TileArgs {
 size_t tile_lds_bytes(bool c64, int L, bool diag);
 // Launches one pass: 2^(L-K) threads per work-group; each work-group walks
 // tiles g = blockIdx.x, blockIdx.x + gridDim.x, ... below 2^nnon.
-// prefetch: load the next tile into registers while the current one is processed.
-hipError_t launch_tile(const TileArgs &a, int K, bool c64, bool prefetch, hipStream_t st);
+hipError_t launch_tile(const TileArgs &a, int K, bool c64, hipStream_t st);
+
+// One task of a batched level launch: tiles [tile0, tile0 + ntiles) of pass
+// `pass` (an index into BatchArgs.passes) of circuit `circ`.
+struct BatchTask {
+    int32_t pass;
+    int32_t circ;
+    uint32_t tile0;
+    uint32_t ntiles;
+};
+
+struct BatchArgs {
+    const BatchTask *tasks;     // all levels, level by level
+    const TileArgs *passes;     // tile geometry K = 4 for every pass
+    uint64_t *t_start;          // per task: device clock when it started
+    uint64_t *t_end;            // per task: device clock when it ended
+    uint32_t task0, task_end;   // the tasks of this launch's level
+};
+
+// One level of a batch: 2^(L-4) threads per work-group (the largest tile of
+// the dtype), blocks_per_cu work-groups per CU taking tasks round-robin.
+hipError_t launch_level(const BatchArgs &b, bool c64, int blocks_per_cu, hipStream_t st);
 
 }  // namespace svk

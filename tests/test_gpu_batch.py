@@ -1,0 +1,181 @@
+"""GPU: many circuits in one persistent launch (sv_batch_run) give the same
+result as each circuit run alone, and match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1801_01037_amd as sv
+import qcircuits as qc
+from tests.gpu_helpers import DTYPE_IDS, DTYPES, assert_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _specs(count, seed, n_lo=10, n_hi=18, d_lo=4, d_hi=30):
+    return qc.batch_specs(seed, count, n_lo, n_hi, d_lo, d_hi)
+
+
+def _run_alone(n, dtype, g):
+    h = sv.sv_create(n, dtype)
+    try:
+        sv.sv_run_circuit(h, g, sv.SV_FUSE)
+        return sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+
+
+def test_batch_of_full_tiles():
+    """Every circuit fills a whole tile (complex128, n >= 12): all threads of
+    each work-group hold amplitudes."""
+    dtype = sv.SV_C128
+    specs = _specs(6, 41, 12, 16, 4, 12)
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_run(b, plans)
+        sv.sv_batch_times(b, len(plans))
+        outs = [sv.sv_copy_out(h) for h in states]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    for (n, d, s), g, got in zip(specs, circuits, outs):
+        assert np.array_equal(got, _run_alone(n, dtype, g)), (n, d)
+
+
+@pytest.mark.parametrize("flags", [0, sv.SV_GRAPH], ids=["launches", "graph"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
+def test_batch_equals_alone_and_oracle(dtype, flags):
+    specs = _specs(24, 5)
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_run(b, plans, flags=flags)
+        start, end = sv.sv_batch_times(b, len(plans))
+        outs = [sv.sv_copy_out(h) for h in states]
+        if flags:                                   # replay the captured graph
+            for h in states:
+                sv.sv_reset(h, 0)
+                sv.sv_synchronize(h)
+            sv.sv_batch_run(b, plans, flags=flags)
+            sv.sv_batch_times(b, len(plans))
+            again = [sv.sv_copy_out(h) for h in states]
+            assert all(np.array_equal(x, y) for x, y in zip(outs, again))
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    assert np.all(end >= start) and np.all(start >= 0)
+    for (n, d, s), g, got in zip(specs, circuits, outs):
+        alone = _run_alone(n, dtype, g)
+        assert np.array_equal(got, alone), (n, d)          # same alone and in the mix
+        if n <= 16:
+            assert_close(got, oracle.simulate(n, g), dtype, len(g), f"batch n={n} d={d}")
+
+
+def test_batch_in_pass_ranges_and_configs():
+    """Running plans in two chunks of passes, under different launch
+    configurations, gives the same bits as one full run."""
+    dtype = sv.SV_C64
+    specs = _specs(12, 9, 12, 20, 10, 40)
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    ref = [_run_alone(n, dtype, g) for (n, _, _), g in zip(specs, circuits)]
+    for bpc, tpt in [(1, 1), (2, 8), (4, 64)]:
+        states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+        plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+        b = sv.sv_batch_create(dtype)
+        try:
+            sv.sv_batch_config(b, bpc, tpt)
+            npass = np.array([sv.sv_plan_passes(p) for p in plans], dtype=np.int32)
+            half = npass // 2
+            sv.sv_batch_run(b, plans, np.zeros_like(half), half)
+            sv.sv_batch_run(b, plans, half, npass - half)
+            outs = [sv.sv_copy_out(h) for h in states]
+        finally:
+            sv.sv_batch_destroy(b)
+            for p in plans:
+                sv.sv_plan_destroy(p)
+            for h in states:
+                sv.sv_destroy(h)
+        for r, got in zip(ref, outs):
+            assert np.array_equal(r, got), (bpc, tpt)
+
+
+def test_run_plan_matches_fused_run():
+    n, dtype = 17, sv.SV_C128
+    g = qc.workload_layers_qft(n, 12, 3)
+    h = sv.sv_create(n, dtype)
+    try:
+        p = sv.sv_plan_create(h, g)
+        k = sv.sv_plan_passes(p)
+        sv.sv_run_plan(p, 0, k // 2)
+        sv.sv_run_plan(p, k // 2, k - k // 2)
+        got = sv.sv_copy_out(h)
+        sv.sv_plan_destroy(p)
+    finally:
+        sv.sv_destroy(h)
+    assert np.array_equal(got, _run_alone(n, dtype, g))
+
+
+def test_batch_rejects_bad_requests():
+    h1 = sv.sv_create(10, sv.SV_C64)
+    h2 = sv.sv_create(10, sv.SV_C128)
+    g = qc.layer_circuit(10, 2, 1)
+    p1, p2 = sv.sv_plan_create(h1, g), sv.sv_plan_create(h2, g)
+    b = sv.sv_batch_create(sv.SV_C64)
+    try:
+        with pytest.raises(sv.SVError):
+            sv.sv_batch_run(b, [p1, p2])               # mixed dtypes
+        with pytest.raises(sv.SVError):
+            sv.sv_batch_run(b, [p1, p1])               # one state twice
+        with pytest.raises(sv.SVError):
+            sv.sv_batch_run(b, [p1], [0], [10 ** 6])   # pass range outside the plan
+        with pytest.raises(sv.SVError):
+            sv.sv_batch_config(b, 0, 8)
+    finally:
+        sv.sv_batch_destroy(b)
+        sv.sv_plan_destroy(p1)
+        sv.sv_plan_destroy(p2)
+        sv.sv_destroy(h1)
+        sv.sv_destroy(h2)
+
+
+@pytest.mark.skip(reason="the persistent work-queue batch kernel this exercised is switched off: "
+                         "it hung on the GPU twice (relaxed, then acquire polls of the "
+                         "per-circuit counters); batches now run one launch per pass level "
+                         "with no waits, and sv_batch_set_wait_limit is gone with it")
+def test_expired_waits_are_reported_and_the_launch_ends():
+    """A zero wait bound makes every dependent task give up (forced from the
+    host); the launch still ends and the run reports SV_EDEVICE."""
+    dtype = sv.SV_C64
+    n = 16
+    g = qc.layer_circuit(n, 30, 2)
+    h = sv.sv_create(n, dtype)
+    p = sv.sv_plan_create(h, g)
+    b = sv.sv_batch_create(dtype)
+    try:
+        assert sv.sv_plan_passes(p) > 1
+        sv.sv_batch_set_wait_limit(b, 0.0)
+        sv.sv_batch_run(b, [p])
+        with pytest.raises(sv.SVError) as ei:
+            sv.sv_batch_times(b, 1)
+        assert ei.value.status == sv.SV_EDEVICE
+        sv.sv_batch_set_wait_limit(b, 10000.0)     # a normal run afterwards is fine
+        sv.sv_reset(h, 0)
+        sv.sv_synchronize(h)
+        sv.sv_batch_run(b, [p])
+        sv.sv_batch_times(b, 1)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_batch_destroy(b)
+        sv.sv_plan_destroy(p)
+        sv.sv_destroy(h)
+    assert np.array_equal(got, _run_alone(n, dtype, g))
