@@ -42,6 +42,10 @@ def parse():
                     help="CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-circuits", type=int, default=512)
+    ap.add_argument("--serving-arrivals", type=int, default=0,
+                    help="also run a short serving sample with this many arrivals")
     return ap.parse_args()
 
 
@@ -109,6 +113,76 @@ def roofline(prof):
             "bytes_per_launch": per_launch}
 
 
+def run_batched(sv, torch, count, seed=3):
+    """512 independent layered circuits, n ~ U{10..24}, depth ~ U{20..200},
+    complex64, run as one batch (HIP graph) with the autotuned launch
+    configuration; latency of each circuit from the device clock."""
+    import qcircuits as qc
+    from paper_1801_01037_amd import autotune
+    specs = qc.batch_specs(seed, count, 10, 24, 20, 200)
+    stream = torch.cuda.Stream()
+    states, plans, gates = [], [], 0
+    t0 = time.perf_counter()
+    for n, d, gs in specs:
+        g = qc.layer_circuit(n, d, gs)
+        gates += len(g)
+        st = sv.StateVector(n, sv.SV_C64, stream=stream)
+        states.append(st)
+        plans.append(sv.sv_plan_create(st.handle, g))
+    plan_s = time.perf_counter() - t0
+    tune_n = min(64, count)
+    (bpc, tpt), tune_times = autotune.tune_batch(sv.SV_C64, plans[:tune_n], f"layers-{tune_n}",
+                                                 stream=stream)
+    b = sv.sv_batch_create(sv.SV_C64, stream.cuda_stream)
+    try:
+        sv.sv_batch_config(b, bpc, tpt)
+        for st in states:
+            st.reset(0)
+        sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)      # capture + first replay (warm-up)
+        stream.synchronize()
+        for st in states:
+            st.reset(0)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)
+        stream.synchronize()
+        wall = time.perf_counter() - t1
+        start, end = sv.sv_batch_times(b, count)
+        norms = [st.norm() for st in states[:8]]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for st in states:
+            st.close()
+        torch.cuda.empty_cache()
+    return {"circuits": count, "gates": gates, "dtype": "f32",
+            "workload": "layered Haar-SU(2)/CNOT circuits, n ~ U{10..24}, depth ~ U{20..200}, "
+                        "complex64, one level-synchronous batch replayed from a HIP graph",
+            "p50_ms": round(float(np.percentile(end, 50)), 3),
+            "p99_ms": round(float(np.percentile(end, 99)), 3),
+            "makespan_ms": round(float(end.max()), 3), "wall_ms": round(wall * 1e3, 3),
+            "gates_per_s": round(gates / wall, 1), "circuits_per_s": round(count / wall, 2),
+            "autotuned": {"blocks_per_cu": bpc, "tiles_per_task": tpt,
+                          "candidates_ms": {k: round(v, 3) for k, v in tune_times.items()}},
+            "host_planning_s": round(plan_s, 2),
+            "norm_max_dev": max(abs(x - 1.0) for x in norms)}
+
+
+def run_serving(arrivals, rate=100.0, seed=0):
+    from paper_1801_01037_amd import serving
+    reqs = serving.poisson_requests(rate, arrivals, seed)
+    srv = serving.Server(chunk=8)
+    try:
+        stats = srv.run(reqs)
+    finally:
+        srv.close()
+    stats["offered_rps"] = rate
+    stats["workload"] = ("Poisson arrivals, n ~ U{12..28}, depth ~ U{10..100}, complex64 or "
+                         "complex128 (p = 1/2), continuous batching")
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+
+
 def cpu_baseline(n, budget_s):
     """The oracle stepping the same 30-qubit layered circuit, gate by gate, on one
     host thread, until `budget_s` seconds have been spent (at least 2 gates)."""
@@ -157,6 +231,15 @@ def main():
                    "effective_hbm_frac": round(r64["effective_hbm_frac"], 4),
                    "speedup_vs_c128": round(r64["gates_per_s"] / r128["gates_per_s"], 3),
                    "roofline": roofline(r64["profile"]), "norm": r64["norm"]}
+    batched = None
+    if not args.no_batched:
+        log(f"[bench] batched: {args.batched_circuits} circuits")
+        batched = run_batched(sv, torch, args.batched_circuits)
+        log(f"[bench] batched p50 {batched['p50_ms']} ms p99 {batched['p99_ms']} ms")
+    serving_stats = None
+    if args.serving_arrivals:
+        log(f"[bench] serving: {args.serving_arrivals} arrivals")
+        serving_stats = run_serving(args.serving_arrivals)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
@@ -182,6 +265,8 @@ def main():
         "roofline": roofline(r128["profile"]),
         "cpu_baseline": cpu,
         "c64": out_c64,
+        "batched": batched,
+        "serving": serving_stats,
         "kernels_c128": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),
                              "GBps": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)}
                          for k, v in r128["profile"].items()},
