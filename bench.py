@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--batched-circuits", type=int, default=512)
     ap.add_argument("--serving-arrivals", type=int, default=0,
                     help="also run a short serving sample with this many arrivals")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a plain copy kernel of "
+                         "known size, for scaling memory-traffic counters)")
     return ap.parse_args()
 
 
@@ -101,7 +104,35 @@ def run_dtype(sv, torch, dtype, n, steps, warmup, flags):
     }
 
 
-def roofline(prof):
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = {"tile": "kernels_tile.hip", "pair": "kernels_gate.hip",
+                 "pair_ctrl": "kernels_gate.hip", "swap": "kernels_gate.hip",
+                 "diag": "kernels_gate.hip", "dense": "kernels_dense.hip"}
+
+
+def measured_traffic(cls, dtype_tag):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summaries (profiles/*_traffic.txt), or None when there is none or
+    the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = KERNEL_SOURCE.get(cls)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_1801_01037_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))):
+        with open(path) as f:
+            for ln in f:
+                tok = ln.split()
+                if len(tok) == 7 and not ln.startswith("#") and tok[0] == cls and tok[1] == dtype_tag:
+                    if tok[6] != sha:
+                        return None
+                    return (float(tok[2]) * float(tok[4]) + float(tok[3]) * float(tok[5])) * 1024
+    return None
+
+
+def roofline(prof, dtype_tag):
     """Roofline line of the kernel class with the most device time."""
     cls, d = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = d["total_ms"] / d["launches"]
@@ -109,8 +140,8 @@ def roofline(prof):
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     return {"kernel": cls, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "launches": d["launches"], "avg_ms": round(avg_ms, 4),
-            "bytes_per_launch": per_launch}
+            "traffic": measured_traffic(cls, dtype_tag), "launches": d["launches"],
+            "avg_ms": round(avg_ms, 4), "bytes_per_launch": per_launch}
 
 
 def run_batched(sv, torch, count, seed=3):
@@ -217,6 +248,13 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.calibration_copy_mib:
+        src = torch.ones(args.calibration_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
+        del src, dst
     flags = sv.SV_FUSE if args.mode == "fused" else 0
     n = args.qubits
     log(f"[bench] c128 n={n} mode={args.mode} steps={args.steps} warmup={args.warmup}")
@@ -230,7 +268,7 @@ def main():
                    "ms_per_step": round(r64["ms_per_step"], 3),
                    "effective_hbm_frac": round(r64["effective_hbm_frac"], 4),
                    "speedup_vs_c128": round(r64["gates_per_s"] / r128["gates_per_s"], 3),
-                   "roofline": roofline(r64["profile"]), "norm": r64["norm"]}
+                   "roofline": roofline(r64["profile"], "c64"), "norm": r64["norm"]}
     batched = None
     if not args.no_batched:
         log(f"[bench] batched: {args.batched_circuits} circuits")
@@ -262,7 +300,7 @@ def main():
                    "n_qubits": n, "gates_per_step": r128["gates_per_step"],
                    "mode": args.mode, "parallelism": "single GPU"},
         "effective_hbm_frac": round(r128["effective_hbm_frac"], 4),
-        "roofline": roofline(r128["profile"]),
+        "roofline": roofline(r128["profile"], "c128"),
         "cpu_baseline": cpu,
         "c64": out_c64,
         "batched": batched,
