@@ -157,6 +157,57 @@ __device__ __forceinline__ void apply_pair(AmpT<C64> (&v)[1 << K], const uint32_
     }
 }
 
+// A 4x4 unitary on register positions P0 < P1: each quad of amplitudes that
+// differ only in those two bits is multiplied by the matrix.
+template <bool C64, int K, int P0, int P1>
+__device__ __forceinline__ void u4_pp(AmpT<C64> (&v)[1 << K], COp &op)
+{
+    using R = RealT<C64>;
+    using A = AmpT<C64>;
+    constexpr int NR = 1 << K;
+    constexpr int b0 = 1 << P0, b1 = 1 << P1;
+    R m[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) m[k] = C64 ? R(op.mf4[k]) : R(op.m4[k]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r & (b0 | b1)) continue;
+        const A x[4] = {v[r], v[r | b0], v[r | b1], v[r | b0 | b1]};
+        A y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const R mr = m[(4 * i + j) * 2], mi = m[(4 * i + j) * 2 + 1];
+                re += mr * x[j].x - mi * x[j].y;
+                im += mr * x[j].y + mi * x[j].x;
+            }
+            y[i].x = re;
+            y[i].y = im;
+        }
+        v[r] = y[0];
+        v[r | b0] = y[1];
+        v[r | b1] = y[2];
+        v[r | b0 | b1] = y[3];
+    }
+}
+
+template <bool C64, int K>
+__device__ __forceinline__ void apply_u4(AmpT<C64> (&v)[1 << K], COp &op)
+{
+    const int code = op.pj * 4 + op.pk;
+    switch (code) {
+    case 0 * 4 + 1: if constexpr (K > 1) u4_pp<C64, K, 0, 1>(v, op); break;
+    case 0 * 4 + 2: if constexpr (K > 2) u4_pp<C64, K, 0, 2>(v, op); break;
+    case 0 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 0, 3>(v, op); break;
+    case 1 * 4 + 2: if constexpr (K > 2) u4_pp<C64, K, 1, 2>(v, op); break;
+    case 1 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 1, 3>(v, op); break;
+    case 2 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 2, 3>(v, op); break;
+    default: break;
+    }
+}
+
 template <bool C64, int K>
 __device__ __forceinline__ void apply_diag(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
                                            COp &op, CPivot *pivots, int L,
@@ -253,6 +304,10 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                     COp &op = ops[G.op0 + oi];
                     if (op.kind == TOP_DIAG) {
                         apply_diag<C64, K>(v, li, op, pivots, a.L, G, gbase, tid, tab);
+                        continue;
+                    }
+                    if (op.kind == TOP_U4) {
+                        apply_u4<C64, K>(v, op);
                         continue;
                     }
                     if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) continue;

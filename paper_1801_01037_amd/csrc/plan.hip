@@ -61,7 +61,147 @@ struct POp {
     double m[8] = {};
     std::vector<PPivot> piv;
     std::vector<int> gates;
+    int q0 = -1, q1 = -1;      // TOP_U4: its two qubits, q0 < q1
+    double m4[32] = {};        // TOP_U4: 4x4, basis b0 + 2 b1 (b0 = bit q0, b1 = bit q1)
 };
+
+// Qubits an op touches (a diagonal op: its pivots and weight bits).
+uint64_t op_qmask(const POp &op)
+{
+    if (op.kind == TOP_U4) return (uint64_t(1) << op.q0) | (uint64_t(1) << op.q1);
+    if (op.kind != TOP_DIAG)
+        return (uint64_t(1) << op.target) | (op.control >= 0 ? uint64_t(1) << op.control : 0);
+    uint64_t m = 0;
+    for (const PPivot &P : op.piv) {
+        m |= uint64_t(1) << P.p;
+        for (const DTerm &t : P.terms)
+            if (t.wbit >= 0) m |= uint64_t(1) << t.wbit;
+    }
+    return m;
+}
+
+// Applies a 2x2 (optionally controlled) op to the 4 columns of a 4x4 matrix
+// over qubits (q0, q1); column-major work on (re, im) pairs.
+void apply_to_4x4(const POp &op, int q0, double *mat /* 4x4 complex, row major */)
+{
+    const int t = op.target == q0 ? 0 : 1;
+    const int c = op.control < 0 ? -1 : (op.control == q0 ? 0 : 1);
+    double g[8];
+    if (op.kind == TOP_SWAP) {
+        const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+        std::memcpy(g, x, sizeof g);
+    } else {
+        std::memcpy(g, op.m, sizeof g);
+    }
+    for (int col = 0; col < 4; ++col)
+        for (int i0 = 0; i0 < 4; ++i0) {
+            if ((i0 >> t) & 1) continue;
+            if (c >= 0 && !((i0 >> c) & 1)) continue;
+            const int i1 = i0 | (1 << t);
+            double *a = mat + (i0 * 4 + col) * 2, *b = mat + (i1 * 4 + col) * 2;
+            const double ar = a[0], ai = a[1], br = b[0], bi = b[1];
+            a[0] = g[0] * ar - g[1] * ai + g[2] * br - g[3] * bi;
+            a[1] = g[0] * ai + g[1] * ar + g[2] * bi + g[3] * br;
+            b[0] = g[4] * ar - g[5] * ai + g[6] * br - g[7] * bi;
+            b[1] = g[4] * ai + g[5] * ar + g[6] * bi + g[7] * br;
+        }
+}
+
+// Inside one register group, merges runs of ops that act on at most two
+// register qubits into one op: a 4x4 over the two qubits, or a product 2x2 on
+// one. Ops are taken in the light-cone order of the pass planner: an op may
+// move ahead of ops it shares no qubit with. Ops with a control outside the
+// register qubits, and diagonal ops, are kept as they are. A run of a single op
+// is kept too (an exchange or a 2x2 is cheaper than a 4x4).
+std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq)
+{
+    auto absorbable = [&](const POp &op) {
+        if (op.kind != TOP_U && op.kind != TOP_SWAP) return false;
+        return op.control < 0 || ((regq >> op.control) & 1);
+    };
+    std::vector<POp> out;
+    while (!ops.empty()) {
+        if (!absorbable(ops.front())) {
+            out.push_back(std::move(ops.front()));
+            ops.erase(ops.begin());
+            continue;
+        }
+        // Seed the block with the qubits of the first two-qubit op that can
+        // join, so that it collects the one-qubit ops around that gate.
+        uint64_t seed = op_qmask(ops.front());
+        for (const POp &op : ops)
+            if (absorbable(op) && __builtin_popcountll(op_qmask(op)) == 2) {
+                seed = op_qmask(op);
+                break;
+            }
+        std::vector<POp> members, next;
+        for (int attempt = 0; attempt < 2 && members.empty(); ++attempt) {
+            if (attempt == 1) seed = op_qmask(ops.front());   // the seed could not join
+            uint64_t P = seed, blocked = 0;
+            next.clear();
+            for (POp &op : ops) {
+                const uint64_t qm = op_qmask(op);
+                if ((qm & blocked) || !absorbable(op) || __builtin_popcountll(P | qm) > 2) {
+                    blocked |= qm;
+                    next.push_back(op);
+                    continue;
+                }
+                P |= qm;
+                members.push_back(op);
+            }
+        }
+        uint64_t P = 0;
+        for (const POp &m : members) P |= op_qmask(m);
+        if (members.size() == 1) {
+            out.push_back(std::move(members.front()));
+        } else if (__builtin_popcountll(P) == 1) {
+            // product of 2x2s on one qubit (each later op multiplies on the left)
+            POp f;
+            f.kind = TOP_U;
+            f.target = members.front().target;
+            double acc[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+            for (const POp &mop : members) {
+                double g[8];
+                if (mop.kind == TOP_SWAP) {
+                    const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+                    std::memcpy(g, x, sizeof g);
+                } else {
+                    std::memcpy(g, mop.m, sizeof g);
+                }
+                double r[8];
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) {
+                        double re = 0, im = 0;
+                        for (int k = 0; k < 2; ++k) {
+                            const double gr = g[(2 * i + k) * 2], gi = g[(2 * i + k) * 2 + 1];
+                            const double ar = acc[(2 * k + j) * 2], ai = acc[(2 * k + j) * 2 + 1];
+                            re += gr * ar - gi * ai;
+                            im += gr * ai + gi * ar;
+                        }
+                        r[(2 * i + j) * 2] = re;
+                        r[(2 * i + j) * 2 + 1] = im;
+                    }
+                std::memcpy(acc, r, sizeof acc);
+                f.gates.insert(f.gates.end(), mop.gates.begin(), mop.gates.end());
+            }
+            std::memcpy(f.m, acc, sizeof acc);
+            out.push_back(std::move(f));
+        } else {
+            POp f;
+            f.kind = TOP_U4;
+            f.q0 = __builtin_ctzll(P);
+            f.q1 = 63 - __builtin_clzll(P);
+            for (int i = 0; i < 4; ++i) f.m4[(i * 4 + i) * 2] = 1.0;
+            for (const POp &mop : members) {
+                apply_to_4x4(mop, f.q0, f.m4);
+                f.gates.insert(f.gates.end(), mop.gates.begin(), mop.gates.end());
+            }
+            out.push_back(std::move(f));
+        }
+        ops.swap(next);
+    }
+    return out;
+}
 
 struct PGroup {
     std::vector<int> S;   // local positions
@@ -75,6 +215,7 @@ struct PPass {
 
 struct TileGeom {
     int L, K, nlow;
+    bool fuse4;     // merge register-local runs into 4x4 ops
 };
 
 TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
@@ -88,6 +229,8 @@ TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
     if (const char *e = std::getenv("SV_TILE_NLOW")) nlow = std::atoi(e);
+    g.fuse4 = true;
+    if (const char *e = std::getenv("SV_TILE_FUSE4")) g.fuse4 = std::atoi(e) != 0;
     if (force_k > 0) K = force_k;
     g.L = std::min(n, L);
     g.K = std::min(g.L, K);
@@ -219,27 +362,59 @@ std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Ite
         auto local = [&](int q) {
             return int(std::lower_bound(pass.T.begin(), pass.T.end(), q) - pass.T.begin());
         };
-        // Groups: consecutive ops whose targets fit in K register bits.
-        PGroup cur;
-        for (POp &op : ops) {
-            if (op.kind != TOP_DIAG) {
-                const int p = local(op.target);
-                const bool have = std::find(cur.S.begin(), cur.S.end(), p) != cur.S.end();
-                if (!have && int(cur.S.size()) >= geo.K) {
-                    pass.groups.push_back(std::move(cur));
-                    cur = PGroup();
+        // Groups, by the light-cone rule: a group gets up to K register
+        // qubits (a target, and its control when it is a tile qubit and
+        // fits), and takes every op whose target is a register qubit and that
+        // touches no qubit of an op left for a later group. Diagonal ops need
+        // no register qubit. Ops only move ahead of ops on other qubits.
+        {
+            std::vector<POp> rem_ops = std::move(ops);
+            while (!rem_ops.empty()) {
+                PGroup cur;
+                uint64_t Sq = 0, blocked = 0;
+                std::vector<POp> later;
+                for (POp &op : rem_ops) {
+                    const uint64_t qm = op_qmask(op);
+                    if (qm & blocked) {
+                        blocked |= qm;
+                        later.push_back(std::move(op));
+                        continue;
+                    }
+                    if (op.kind == TOP_DIAG) {
+                        cur.ops.push_back(std::move(op));
+                        continue;
+                    }
+                    const uint64_t need = uint64_t(1) << op.target;
+                    uint64_t want = need;
+                    if (op.control >= 0 && ((Tm >> op.control) & 1)) want |= uint64_t(1) << op.control;
+                    if (__builtin_popcountll(Sq | want) <= geo.K) {
+                        Sq |= want;
+                    } else if (__builtin_popcountll(Sq | need) <= geo.K) {
+                        Sq |= need;
+                    } else {
+                        blocked |= qm;
+                        later.push_back(std::move(op));
+                        continue;
+                    }
+                    cur.ops.push_back(std::move(op));
                 }
-                if (std::find(cur.S.begin(), cur.S.end(), p) == cur.S.end()) cur.S.push_back(p);
+                for (int b = 0; b < 64; ++b)
+                    if ((Sq >> b) & 1) cur.S.push_back(local(b));
+                pass.groups.push_back(std::move(cur));
+                rem_ops.swap(later);
             }
-            cur.ops.push_back(std::move(op));
         }
-        if (!cur.ops.empty()) pass.groups.push_back(std::move(cur));
         for (PGroup &g : pass.groups) {
             // Pad S with the highest unused local bits so the threads of a
             // wave differ in low local bits (contiguous LDS slots).
             for (int b = geo.L - 1; b >= 0 && int(g.S.size()) < geo.K; --b)
                 if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) g.S.push_back(b);
             std::sort(g.S.begin(), g.S.end());
+            if (geo.fuse4 && geo.K >= 2) {
+                uint64_t regq = 0;
+                for (int sidx : g.S) regq |= uint64_t(1) << pass.T[sidx];
+                g.ops = fuse_group(std::move(g.ops), regq);
+            }
         }
         passes.push_back(std::move(pass));
         rem.swap(next);
@@ -314,6 +489,12 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                         f.pivots.push_back(tp);
                         flops += 1.5 * N * double(P.terms.size());
                     }
+                } else if (op.kind == TOP_U4) {
+                    to.pj = int(std::find(g.S.begin(), g.S.end(), local(op.q0)) - g.S.begin());
+                    to.pk = int(std::find(g.S.begin(), g.S.end(), local(op.q1)) - g.S.begin());
+                    std::memcpy(to.m4, op.m4, sizeof to.m4);
+                    for (int k = 0; k < 32; ++k) to.mf4[k] = float(op.m4[k]);
+                    flops += 32.0 * N;
                 } else {
                     const int p = local(op.target);
                     to.pj = int(std::find(g.S.begin(), g.S.end(), p) - g.S.begin());

@@ -24,7 +24,7 @@ constexpr int kTileL128 = 12, kTileK128 = 4;   // 64 KiB of complex128 per tile,
 constexpr int kTileL64 = 13, kTileK64 = 4;     // 64 KiB of complex64 per tile, 512 threads
 constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
 
-enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2 };
+enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2, TOP_U4 = 3 };
 
 // A diagonal op multiplies each amplitude by e^{2 pi i T / 2^64}, where T is
 // an exact uint64 sum (mod one full turn) over the op's pivots:
@@ -45,14 +45,19 @@ constexpr int kTileMaxPivots = 8;
 
 struct TileOp {
     int32_t kind;
-    int32_t pj;        // TOP_U / TOP_SWAP: target as a position in the group's S
+    int32_t pj;        // TOP_U / TOP_SWAP: target as a position in the group's S;
+                       // TOP_U4: the lower of its two positions
     int32_t lctrl;     // control as a local tile bit, or -1
     int32_t octrl;     // control as a global index bit outside the tile, or -1
     int32_t piv0;      // TOP_DIAG: first pivot
     int32_t npiv;      // TOP_DIAG: number of pivots (<= kTileMaxPivots)
-    int32_t pad0, pad1;
+    int32_t pk;        // TOP_U4: the higher of its two positions
+    int32_t pad1;
     double m[8];       // 2x2 in FP64
     float mf[8];       // the same rounded to FP32 (complex64 states)
+    double m4[32];     // TOP_U4: 4x4 in FP64, row major, (re, im); basis index
+                       // b0 + 2 b1 with b0 the bit at position pj, b1 at pk
+    float mf4[32];     // the same rounded to FP32
 };
 
 struct TileGroup {

@@ -23,7 +23,8 @@ def _qubits(g):
     return {int(g["target"])} | ({int(g["control"])} if int(g["control"]) >= 0 else set())
 
 
-def check_plan_order(n, dtype, gates):
+def check_plan_order(n, dtype, gates, strict=False):
+    """strict: every non-diagonal gate has an op of its own (no 4x4 fusion)."""
     gate_op, passes, groups, ops = sv.sv_plan_inspect(n, dtype, gates)
     assert (gate_op >= 0).all() and (gate_op < ops).all()
     diag = np.array([_is_diag(g) for g in gates])
@@ -37,10 +38,20 @@ def check_plan_order(n, dtype, gates):
                 i, j = idx[a], idx[b]
                 if diag[i] and diag[j]:
                     continue
-                assert gate_op[i] < gate_op[j], (q, i, j, gate_op[i], gate_op[j])
-    nondiag_ops = gate_op[~diag]
-    assert len(set(nondiag_ops.tolist())) == len(nondiag_ops)   # one op per such gate
+                # gates merged into one op are applied as one product, in order
+                if strict:
+                    assert gate_op[i] < gate_op[j], (q, i, j, gate_op[i], gate_op[j])
+                else:
+                    assert gate_op[i] <= gate_op[j], (q, i, j, gate_op[i], gate_op[j])
+    if strict:
+        nondiag_ops = gate_op[~diag]
+        assert len(set(nondiag_ops.tolist())) == len(nondiag_ops)   # one op per such gate
     return passes, groups, ops
+
+
+@pytest.fixture
+def no_fusion(monkeypatch):
+    monkeypatch.setenv("SV_TILE_FUSE4", "0")
 
 
 def mixed_circuit(n, count, seed):
@@ -86,6 +97,21 @@ def test_mixed_circuit_plans_are_legal(n):
         g = mixed_circuit(n, 300, seed + 100 * n)
         for dtype in (sv.SV_C128, sv.SV_C64):
             check_plan_order(n, dtype, g)
+
+
+@pytest.mark.parametrize("n", [5, 13, 22])
+def test_unfused_plans_keep_every_order(n, no_fusion):
+    for seed in range(2):
+        g = mixed_circuit(n, 300, seed + 7 * n)
+        check_plan_order(n, sv.SV_C128, g, strict=True)
+    check_plan_order(30, sv.SV_C128, qc.layer_circuit(30, 20, 1), strict=True)
+
+
+def test_fusion_reduces_ops():
+    g = qc.layer_circuit(30, 20, 1)
+    _, passes, groups, fused_ops = sv.sv_plan_inspect(30, sv.SV_C128, g)
+    assert fused_ops < 0.62 * len(g)
+    assert groups < 3 * passes          # light-cone groups fill the register qubits
 
 
 def test_plan_rejects_bad_gates():
