@@ -99,9 +99,28 @@ __device__ __forceinline__ AmpT<C64> turn_phase(uint64_t T, const AmpT<C64> *tab
     return cmul(cmul(e1, e2), e3);
 }
 
+template <typename R>
+__device__ __forceinline__ R fmadd(R a, R b, R c)
+{
+    if constexpr (std::is_same_v<R, float>) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// Every op reads the amplitudes from `in` and writes all of them to `out`;
+// the group loop alternates two arrays, so results never need copying back.
+template <bool C64, int K>
+using Amps = AmpT<C64>[1 << K];
+
+template <bool C64, int K>
+__device__ __forceinline__ void copy_amps(const Amps<C64, K> &in, Amps<C64, K> &out)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) out[r] = in[r];
+}
+
 template <bool C64, int K, int PJ, bool SWAP, bool CTRL>
-__device__ __forceinline__ void pair_pj(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
-                                        COp &op)
+__device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &out,
+                                        const uint32_t (&li)[1 << K], COp &op)
 {
     using R = RealT<C64>;
     using A = AmpT<C64>;
@@ -122,45 +141,56 @@ __device__ __forceinline__ void pair_pj(AmpT<C64> (&v)[1 << K], const uint32_t (
         if (r & (1 << PJ)) continue;
         constexpr int bit = 1 << PJ;
         const int r1 = r | bit;
-        const A a = v[r], b = v[r1];
+        const A a = in[r], b = in[r1];
         A na, nb;
         if constexpr (SWAP) {
             na = b;
             nb = a;
         } else {
-            na.x = m0 * a.x - m1 * a.y + m2 * b.x - m3 * b.y;
-            na.y = m0 * a.y + m1 * a.x + m2 * b.y + m3 * b.x;
-            nb.x = m4 * a.x - m5 * a.y + m6 * b.x - m7 * b.y;
-            nb.y = m4 * a.y + m5 * a.x + m6 * b.y + m7 * b.x;
+            na.x = fmadd(-m3, b.y, fmadd(m2, b.x, fmadd(-m1, a.y, m0 * a.x)));
+            na.y = fmadd(m3, b.x, fmadd(m2, b.y, fmadd(m1, a.x, m0 * a.y)));
+            nb.x = fmadd(-m7, b.y, fmadd(m6, b.x, fmadd(-m5, a.y, m4 * a.x)));
+            nb.y = fmadd(m7, b.x, fmadd(m6, b.y, fmadd(m5, a.x, m4 * a.y)));
         }
         if constexpr (CTRL) {
             const bool on = (li[r] >> lc) & 1u;
-            v[r] = on ? na : a;
-            v[r1] = on ? nb : b;
+            out[r] = on ? na : a;
+            out[r1] = on ? nb : b;
         } else {
-            v[r] = na;
-            v[r1] = nb;
+            out[r] = na;
+            out[r1] = nb;
         }
     }
 }
 
 template <bool C64, int K, bool SWAP, bool CTRL>
-__device__ __forceinline__ void apply_pair(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
-                                           COp &op)
+__device__ __forceinline__ void apply_pair(const Amps<C64, K> &in, Amps<C64, K> &out,
+                                           const uint32_t (&li)[1 << K], COp &op)
 {
+    // Every arm writes all of `out`, so the other array's old values are dead
+    // here and the two arrays share no live range.
     switch (op.pj) {
-    case 0: pair_pj<C64, K, 0, SWAP, CTRL>(v, li, op); break;
-    case 1: if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(v, li, op); break;
-    case 2: if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(v, li, op); break;
-    case 3: if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(v, li, op); break;
-    default: break;
+    case 0: pair_pj<C64, K, 0, SWAP, CTRL>(in, out, li, op); break;
+    case 1:
+        if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(in, out, li, op);
+        else copy_amps<C64, K>(in, out);
+        break;
+    case 2:
+        if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(in, out, li, op);
+        else copy_amps<C64, K>(in, out);
+        break;
+    case 3:
+        if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(in, out, li, op);
+        else copy_amps<C64, K>(in, out);
+        break;
+    default: copy_amps<C64, K>(in, out); break;   // the planner emits no other position
     }
 }
 
 // A 4x4 unitary on register positions P0 < P1: each quad of amplitudes that
 // differ only in those two bits is multiplied by the matrix.
 template <bool C64, int K, int P0, int P1>
-__device__ __forceinline__ void u4_pp(AmpT<C64> (&v)[1 << K], COp &op)
+__device__ __forceinline__ void u4_pp(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
 {
     using R = RealT<C64>;
     using A = AmpT<C64>;
@@ -172,44 +202,52 @@ __device__ __forceinline__ void u4_pp(AmpT<C64> (&v)[1 << K], COp &op)
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r & (b0 | b1)) continue;
-        const A x[4] = {v[r], v[r | b0], v[r | b1], v[r | b0 | b1]};
-        A y[4];
+        const int idx[4] = {r, r | b0, r | b1, r | b0 | b1};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            R re = 0, im = 0;
+            // one FMA chain per real component: re = sum_j Re(m_ij x_j)
+            R re = m[8 * i] * in[idx[0]].x;
+            R im = m[8 * i] * in[idx[0]].y;
+            re = fmadd(-m[8 * i + 1], in[idx[0]].y, re);
+            im = fmadd(m[8 * i + 1], in[idx[0]].x, im);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 1; j < 4; ++j) {
                 const R mr = m[(4 * i + j) * 2], mi = m[(4 * i + j) * 2 + 1];
-                re += mr * x[j].x - mi * x[j].y;
-                im += mr * x[j].y + mi * x[j].x;
+                re = fmadd(mr, in[idx[j]].x, re);
+                re = fmadd(-mi, in[idx[j]].y, re);
+                im = fmadd(mr, in[idx[j]].y, im);
+                im = fmadd(mi, in[idx[j]].x, im);
             }
-            y[i].x = re;
-            y[i].y = im;
+            out[idx[i]].x = re;
+            out[idx[i]].y = im;
         }
-        v[r] = y[0];
-        v[r | b0] = y[1];
-        v[r | b1] = y[2];
-        v[r | b0 | b1] = y[3];
     }
 }
 
 template <bool C64, int K>
-__device__ __forceinline__ void apply_u4(AmpT<C64> (&v)[1 << K], COp &op)
+__device__ __forceinline__ void apply_u4(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
 {
     const int code = op.pj * 4 + op.pk;
+#define SV_U4_CASE(P0, P1)                                                        \
+    case P0 * 4 + P1:                                                             \
+        if constexpr (K > P1) u4_pp<C64, K, P0, P1>(in, out, op);                 \
+        else copy_amps<C64, K>(in, out);                                          \
+        break;
     switch (code) {
-    case 0 * 4 + 1: if constexpr (K > 1) u4_pp<C64, K, 0, 1>(v, op); break;
-    case 0 * 4 + 2: if constexpr (K > 2) u4_pp<C64, K, 0, 2>(v, op); break;
-    case 0 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 0, 3>(v, op); break;
-    case 1 * 4 + 2: if constexpr (K > 2) u4_pp<C64, K, 1, 2>(v, op); break;
-    case 1 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 1, 3>(v, op); break;
-    case 2 * 4 + 3: if constexpr (K > 3) u4_pp<C64, K, 2, 3>(v, op); break;
-    default: break;
+    SV_U4_CASE(0, 1)
+    SV_U4_CASE(0, 2)
+    SV_U4_CASE(0, 3)
+    SV_U4_CASE(1, 2)
+    SV_U4_CASE(1, 3)
+    SV_U4_CASE(2, 3)
+    default: copy_amps<C64, K>(in, out); break;   // the planner emits no other pair
     }
+#undef SV_U4_CASE
 }
 
 template <bool C64, int K>
-__device__ __forceinline__ void apply_diag(AmpT<C64> (&v)[1 << K], const uint32_t (&li)[1 << K],
+__device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> &out,
+                                           const uint32_t (&li)[1 << K],
                                            COp &op, CPivot *pivots, int L,
                                            CGroup &G, uint64_t gbase, uint32_t tid,
                                            const AmpT<C64> *tab)
@@ -240,9 +278,40 @@ __device__ __forceinline__ void apply_diag(AmpT<C64> (&v)[1 << K], const uint32_
             T[r] += on ? t : 0ull;
         }
     }
+    // A zero turn gives the phase 1 exactly, so every amplitude is multiplied.
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-        if (T[r] != 0) v[r] = cmul(v[r], turn_phase<C64>(T[r], tab));
+    for (int r = 0; r < NR; ++r) out[r] = cmul(in[r], turn_phase<C64>(T[r], tab));
+}
+
+// Applies one op of group G: in -> out.
+template <bool C64, int K>
+__device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &out,
+                                         const uint32_t (&li)[1 << K], COp &op,
+                                         CPivot *pivots, int L, CGroup &G, uint64_t gbase,
+                                         uint32_t tid, const AmpT<C64> *tab)
+{
+    if (op.kind == TOP_DIAG) {
+        apply_diag<C64, K>(in, out, li, op, pivots, L, G, gbase, tid, tab);
+    } else if (op.kind == TOP_U4) {
+        apply_u4<C64, K>(in, out, op);
+    } else if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) {
+        copy_amps<C64, K>(in, out);
+    } else if (op.kind == TOP_SWAP) {
+        if (op.lctrl >= 0) apply_pair<C64, K, true, true>(in, out, li, op);
+        else apply_pair<C64, K, true, false>(in, out, li, op);
+    } else {
+        if (op.lctrl >= 0) apply_pair<C64, K, false, true>(in, out, li, op);
+        else apply_pair<C64, K, false, false>(in, out, li, op);
+    }
+}
+
+// Work-group barrier that orders LDS accesses only: global loads issued
+// before it may still be in flight after it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Processes tiles g = g0, g0 + gstep, ... below gend of the pass `a` with one
@@ -273,14 +342,22 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
 
     for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
+        // Opaque copies made per tile: the per-slot addresses below are
+        // recomputed at each use instead of being hoisted out of the tile loop
+        // and held in registers through all the groups.
+        uint64_t dtv = dt;
+        uint32_t tv = tid;
+        asm volatile("" : "+v"(dtv), "+v"(tv));
         if (active) {
             A pv[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) pv[r] = psi[gbase | dt | roff[r]];
+            for (int r = 0; r < NR; ++r) pv[r] = psi[gbase | dtv | roff[r]];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tid + uint32_t(r) * W)] = pv[r];
+            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tv + uint32_t(r) * W)] = pv[r];
         }
-        __syncthreads();
+        // Barriers order LDS accesses only; the tile's global stores of the
+        // previous turn may still be in flight.
+        lds_barrier();
         for (int gi = 0; gi < a.ngroups; ++gi) {
             CGroup &G = groups[a.group0 + gi];
             if (active) {
@@ -290,7 +367,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
 #pragma unroll
                 for (int k = 0; k < K; ++k) soff[k] = 1u << G.s[k];
                 uint32_t li[NR];
-                A v[NR];
+                A v[NR], w[NR];
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     uint32_t l = lbase;
@@ -300,36 +377,33 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                     li[r] = l;
                     v[r] = lds[lds_slot<C64>(l)];
                 }
-                for (int oi = 0; oi < G.nops; ++oi) {
-                    COp &op = ops[G.op0 + oi];
-                    if (op.kind == TOP_DIAG) {
-                        apply_diag<C64, K>(v, li, op, pivots, a.L, G, gbase, tid, tab);
-                        continue;
-                    }
-                    if (op.kind == TOP_U4) {
-                        apply_u4<C64, K>(v, op);
-                        continue;
-                    }
-                    if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) continue;
-                    const bool ctrl = op.lctrl >= 0;
-                    if (op.kind == TOP_SWAP) {
-                        if (ctrl) apply_pair<C64, K, true, true>(v, li, op);
-                        else apply_pair<C64, K, true, false>(v, li, op);
-                    } else {
-                        if (ctrl) apply_pair<C64, K, false, true>(v, li, op);
-                        else apply_pair<C64, K, false, false>(v, li, op);
-                    }
-                }
+                // Ops alternate v -> w and w -> v; the group ends in either.
+                const int nops = G.nops;
+                for (int oi = 0;; oi += 2) {
+                    if (oi == nops) {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+                        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+                        break;
+                    }
+                    apply_op<C64, K>(v, w, li, ops[G.op0 + oi], pivots, a.L, G, gbase, tid, tab);
+                    if (oi + 1 == nops) {
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = w[r];
+                        break;
+                    }
+                    apply_op<C64, K>(w, v, li, ops[G.op0 + oi + 1], pivots, a.L, G, gbase, tid, tab);
+                }
             }
-            __syncthreads();
+            lds_barrier();
         }
         // Each thread stores the slots it filled, so the next fill needs no barrier.
         if (active) {
-            const uint64_t gb = gbase | dt;
+            uint64_t dts = dt;
+            uint32_t ts = tid;
+            asm volatile("" : "+v"(dts), "+v"(ts));
+            const uint64_t gb = gbase | dts;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(tid + uint32_t(r) * W)];
+            for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(ts + uint32_t(r) * W)];
         }
     }
 }
@@ -379,7 +453,7 @@ __global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
         A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
         run_tiles<C64, K>(a, tile0, uint64_t(tile0) + ntiles, 1, lds, tab);
         if (threadIdx.x == 0) b.t_end[ti] = wall_clock64();
-        __syncthreads();   // the next task reuses LDS
+        lds_barrier();   // the next task reuses LDS
     }
 }
 
