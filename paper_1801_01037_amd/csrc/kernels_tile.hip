@@ -38,7 +38,7 @@ typedef double dv2 __attribute__((ext_vector_type(2)));
 #define SV_CONST __attribute__((address_space(4)))
 typedef const SV_CONST TileGroup CGroup;
 typedef const SV_CONST TileOp COp;
-typedef const SV_CONST TilePivot CPivot;
+typedef const SV_CONST uint64_t CU64;
 
 template <bool C64>
 using RealT = std::conditional_t<C64, float, double>;
@@ -193,7 +193,6 @@ template <bool C64, int K, int P0, int P1>
 __device__ __forceinline__ void u4_pp(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
 {
     using R = RealT<C64>;
-    using A = AmpT<C64>;
     constexpr int NR = 1 << K;
     constexpr int b0 = 1 << P0, b1 = 1 << P1;
     R m[32];
@@ -245,53 +244,70 @@ __device__ __forceinline__ void apply_u4(const Amps<C64, K> &in, Amps<C64, K> &o
 #undef SV_U4_CASE
 }
 
+// Diagonal op (the quadratic phase form described with TileOp): the turn of
+// register combination r is base + sum_{k in r} coef_k + PR(r), so the phase
+// of every amplitude is a product of five evaluated phases and a constant.
 template <bool C64, int K>
-__device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> &out,
-                                           const uint32_t (&li)[1 << K],
-                                           COp &op, CPivot *pivots, int L,
-                                           CGroup &G, uint64_t gbase, uint32_t tid,
-                                           const AmpT<C64> *tab)
+__device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op,
+                                           const uint64_t *dtab, int L, CGroup &G, uint64_t g,
+                                           uint32_t tid, const AmpT<C64> *tab)
 {
+    using A = AmpT<C64>;
     constexpr int NR = 1 << K;
-    uint64_t T[NR];
+    const uint64_t *th = dtab + op.dthr + size_t(tid) * (K + 1);
+    uint64_t base = th[0];
+    uint64_t coef[K];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) T[r] = 0;
-    for (int p = 0; p < op.npiv; ++p) {
-        CPivot &P = pivots[op.piv0 + p];
-        if (P.opivot >= 0 && !((gbase >> P.opivot) & 1ull)) continue;
-        uint64_t c = P.w0;
-        for (int k = 0; k < P.nout; ++k)
-            c += ((gbase >> P.obit[k]) & 1ull) ? P.ow[k] : 0ull;
-        for (int k = 0; k < L - K; ++k)
-            c += ((tid >> k) & 1u) ? P.wl[G.ns[k]] : 0ull;
-        uint64_t ws[K];
+    for (int k = 0; k < K; ++k) coef[k] = th[1 + k];
+    if (op.dout >= 0) {
+        // Weights against the bits of g: uniform byte-table sums (scalar loads).
+        CU64 *bt = (CU64 *)(dtab + op.dout);
+        auto ow = [&](int l) {
+            uint64_t w = 0;
+            for (int b = 0; b < op.dbytes; ++b)
+                w += bt[(size_t(b) * (L + 1) + l) * 256 + ((g >> (8 * b)) & 255u)];
+            return w;
+        };
+        base += ow(L);
+        for (int k = 0; k < L - K; ++k) {
+            const uint64_t w = ow(G.ns[k]);
+            base += ((tid >> k) & 1u) ? w : 0ull;
+        }
 #pragma unroll
-        for (int k = 0; k < K; ++k) ws[k] = P.wl[G.s[k]];
-        const int lp = P.lpivot;
+        for (int k = 0; k < K; ++k) coef[k] += ow(G.s[k]);
+    }
+    A e[NR];
+    A ek[K];
+    e[0] = turn_phase<C64>(base, tab);
+#pragma unroll
+    for (int k = 0; k < K; ++k) ek[k] = turn_phase<C64>(coef[k], tab);
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+        const int k = 31 - __builtin_clz(unsigned(r));
+        e[r] = cmul(e[r ^ (1 << k)], ek[k]);
+    }
+    if (op.pj) {   // register-only terms
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            uint64_t t = c;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (r & (1 << k)) t += ws[k];
-            const bool on = lp < 0 || ((li[r] >> lp) & 1u);
-            T[r] += on ? t : 0ull;
+            A c;
+            if constexpr (C64) { c.x = op.mf4[2 * r]; c.y = op.mf4[2 * r + 1]; }
+            else { c.x = op.m4[2 * r]; c.y = op.m4[2 * r + 1]; }
+            e[r] = cmul(e[r], c);
         }
     }
-    // A zero turn gives the phase 1 exactly, so every amplitude is multiplied.
 #pragma unroll
-    for (int r = 0; r < NR; ++r) out[r] = cmul(in[r], turn_phase<C64>(T[r], tab));
+    for (int r = 0; r < NR; ++r) out[r] = cmul(in[r], e[r]);
 }
 
 // Applies one op of group G: in -> out.
 template <bool C64, int K>
 __device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &out,
                                          const uint32_t (&li)[1 << K], COp &op,
-                                         CPivot *pivots, int L, CGroup &G, uint64_t gbase,
-                                         uint32_t tid, const AmpT<C64> *tab)
+                                         const uint64_t *dtab, int L, CGroup &G, uint64_t g,
+                                         uint64_t gbase, uint32_t tid, const AmpT<C64> *tab)
 {
     if (op.kind == TOP_DIAG) {
-        apply_diag<C64, K>(in, out, li, op, pivots, L, G, gbase, tid, tab);
+        apply_diag<C64, K>(in, out, op, dtab, L, G, g, tid, tab);
     } else if (op.kind == TOP_U4) {
         apply_u4<C64, K>(in, out, op);
     } else if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) {
@@ -329,7 +345,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
     A *psi = static_cast<A *>(a.psi);
     CGroup *groups = (CGroup *)(a.groups);
     COp *ops = (COp *)(a.ops);
-    CPivot *pivots = (CPivot *)(a.pivots);
+    const uint64_t *dtab = a.dtab;
 
     if (a.has_diag) {
         const A *src = static_cast<const A *>(a.phase_tab);
@@ -385,13 +401,13 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                         for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
                         break;
                     }
-                    apply_op<C64, K>(v, w, li, ops[G.op0 + oi], pivots, a.L, G, gbase, tid, tab);
+                    apply_op<C64, K>(v, w, li, ops[G.op0 + oi], dtab, a.L, G, g, gbase, tid, tab);
                     if (oi + 1 == nops) {
 #pragma unroll
                         for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = w[r];
                         break;
                     }
-                    apply_op<C64, K>(w, v, li, ops[G.op0 + oi + 1], pivots, a.L, G, gbase, tid, tab);
+                    apply_op<C64, K>(w, v, li, ops[G.op0 + oi + 1], dtab, a.L, G, g, gbase, tid, tab);
                 }
             }
             lds_barrier();
@@ -444,7 +460,7 @@ __global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
         const uint32_t tile0 = t.tile0, ntiles = t.ntiles;
         const TileArgs SV_CONST &pc = passes[t.pass];
         TileArgs a;
-        a.psi = pc.psi; a.groups = pc.groups; a.ops = pc.ops; a.pivots = pc.pivots;
+        a.psi = pc.psi; a.groups = pc.groups; a.ops = pc.ops; a.dtab = pc.dtab;
         a.phase_tab = pc.phase_tab; a.tmask = pc.tmask; a.omask = pc.omask; a.ntiles = pc.ntiles;
         a.L = pc.L; a.nlow = pc.nlow; a.nnon = pc.nnon; a.group0 = pc.group0;
         a.ngroups = pc.ngroups; a.has_diag = pc.has_diag;

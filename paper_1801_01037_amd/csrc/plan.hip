@@ -265,8 +265,7 @@ Item classify(const sv_gate &g, int idx)
 }
 
 // Emits the pending diagonal terms that touch any qubit of `qm` (all of them
-// when qm is ~0) as diagonal ops appended to `ops`. Terms of one pivot stay
-// together in one op.
+// when qm is ~0) as one diagonal op appended to `ops`.
 void flush_diag(std::map<int, PPivot> &pending, uint64_t qm, std::vector<POp> &ops)
 {
     std::vector<PPivot> out;
@@ -289,12 +288,12 @@ void flush_diag(std::map<int, PPivot> &pending, uint64_t qm, std::vector<POp> &o
         else
             ++it;
     }
-    for (size_t i = 0; i < out.size(); i += kTileMaxPivots) {
+    if (!out.empty()) {
         POp op;
         op.kind = TOP_DIAG;
-        for (size_t j = i; j < std::min(out.size(), i + kTileMaxPivots); ++j) {
-            for (const DTerm &t : out[j].terms) op.gates.push_back(t.gate);
-            op.piv.push_back(std::move(out[j]));
+        for (PPivot &P : out) {
+            for (const DTerm &t : P.terms) op.gates.push_back(t.gate);
+            op.piv.push_back(std::move(P));
         }
         ops.push_back(std::move(op));
     }
@@ -321,6 +320,18 @@ std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Ite
                 continue;
             }
             if (it.diag) {
+                // A pair term needs one of its qubits in the tile (the device
+                // form has no term on two bits of the tile index).
+                if (it.wbit >= 0 && !((Tm >> it.pivot) & 1) && !((Tm >> it.wbit) & 1)) {
+                    if (tcount < geo.L) {
+                        Tm |= uint64_t(1) << it.pivot;
+                        ++tcount;
+                    } else {
+                        next.push_back(it);
+                        blocked |= it.qmask;
+                        continue;
+                    }
+                }
                 PPivot &P = pending[it.pivot];
                 P.p = it.pivot;
                 P.terms.push_back(DTerm{it.wbit, it.turn, it.gate});
@@ -424,10 +435,102 @@ std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Ite
 
 // ---- flattening and execution ---------------------------------------------
 
+// Tables of a diagonal op in one group (the quadratic form described with
+// TileOp): rows of the tile-independent turns for every thread, byte tables
+// over the tile index for weights against qubits outside the tile, and the
+// constant phases of the register-only terms. Returns false for a pair term
+// on two qubits outside the tile (the planner never makes one).
+bool diag_tables(const POp &op, const std::vector<int> &T, const std::vector<int> &S,
+                 const int32_t *ns, int L, int K, uint64_t omask, std::vector<uint64_t> &dtab,
+                 TileOp &to)
+{
+    auto lidx = [&](int q) {
+        const auto it = std::lower_bound(T.begin(), T.end(), q);
+        return (it != T.end() && *it == q) ? int(it - T.begin()) : -1;
+    };
+    auto opos = [&](int q) { return __builtin_popcountll(omask & ((uint64_t(1) << q) - 1)); };
+    std::vector<uint64_t> a(L, 0), Q(size_t(L) * L, 0);
+    std::vector<std::vector<uint64_t>> ow(L + 1);   // [tile bit, or L: one-qubit][outside position]
+    int maxo = -1;
+    auto add_ow = [&](int l, int o, uint64_t t) {
+        if (int(ow[l].size()) <= o) ow[l].resize(o + 1, 0);
+        ow[l][o] += t;
+        maxo = std::max(maxo, o);
+    };
+    for (const PPivot &P : op.piv)
+        for (const DTerm &t : P.terms) {
+            const int lp = lidx(P.p);
+            if (t.wbit < 0) {
+                if (lp >= 0) a[lp] += t.turn;
+                else add_ow(L, opos(P.p), t.turn);
+                continue;
+            }
+            const int lw = lidx(t.wbit);
+            if (lp >= 0 && lw >= 0) Q[size_t(std::min(lp, lw)) * L + std::max(lp, lw)] += t.turn;
+            else if (lp >= 0) add_ow(lp, opos(t.wbit), t.turn);
+            else if (lw >= 0) add_ow(lw, opos(P.p), t.turn);
+            else return false;
+        }
+    auto q = [&](int l0, int l1) { return Q[size_t(std::min(l0, l1)) * L + std::max(l0, l1)]; };
+    const double two_pi = 6.283185307179586476925286766559;
+    bool any = false;
+    for (int r = 0; r < 16; ++r) {
+        uint64_t t = 0;
+        if (r < (1 << K))
+            for (int k = 0; k < K; ++k) {
+                if (!((r >> k) & 1)) continue;
+                t += a[S[k]];
+                for (int k2 = k + 1; k2 < K; ++k2)
+                    if ((r >> k2) & 1) t += q(S[k], S[k2]);
+            }
+        any |= t != 0;
+        const double ang = two_pi * std::ldexp(double(t), -64);
+        to.m4[2 * r] = t ? std::cos(ang) : 1.0;
+        to.m4[2 * r + 1] = t ? std::sin(ang) : 0.0;
+        to.mf4[2 * r] = float(to.m4[2 * r]);
+        to.mf4[2 * r + 1] = float(to.m4[2 * r + 1]);
+    }
+    to.pj = any ? 1 : 0;
+    const int nt = L - K;
+    to.dthr = int(dtab.size());
+    for (uint32_t tid = 0; tid < (1u << nt); ++tid) {
+        uint64_t b0 = 0, cr[kTileMaxK] = {};
+        for (int k = 0; k < nt; ++k) {
+            if (!((tid >> k) & 1)) continue;
+            b0 += a[ns[k]];
+            for (int k2 = k + 1; k2 < nt; ++k2)
+                if ((tid >> k2) & 1) b0 += q(ns[k], ns[k2]);
+            for (int j = 0; j < K; ++j) cr[j] += q(ns[k], S[j]);
+        }
+        dtab.push_back(b0);
+        for (int j = 0; j < K; ++j) dtab.push_back(cr[j]);
+    }
+    if (maxo < 0) {
+        to.dout = -1;
+        to.dbytes = 0;
+        return true;
+    }
+    const int nb = maxo / 8 + 1;
+    to.dout = int(dtab.size());
+    to.dbytes = nb;
+    for (int b = 0; b < nb; ++b)
+        for (int l = 0; l <= L; ++l)
+            for (int v = 0; v < 256; ++v) {
+                uint64_t t = 0;
+                for (int j = 0; j < 8; ++j) {
+                    const int o = 8 * b + j;
+                    if (((v >> j) & 1) && o < int(ow[l].size())) t += ow[l][o];
+                }
+                dtab.push_back(t);
+            }
+    return true;
+}
+
 struct Flat {
+    bool ok = true;                 // false: a diagonal pair term on two outside bits
     std::vector<TileGroup> groups;
     std::vector<TileOp> ops;
-    std::vector<TilePivot> pivots;
+    std::vector<uint64_t> dtab;     // diagonal-op tables
     std::vector<TileArgs> args;   // one per pass (pointers patched after upload)
     std::vector<double> flops;    // per pass
 };
@@ -469,26 +572,9 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                 to.octrl = -1;
                 if (op.kind == TOP_DIAG) {
                     a.has_diag = 1;
-                    to.piv0 = int(f.pivots.size());
-                    to.npiv = int(op.piv.size());
-                    for (const PPivot &P : op.piv) {
-                        TilePivot tp{};
-                        tp.lpivot = ((Tm >> P.p) & 1) ? local(P.p) : -1;
-                        tp.opivot = ((Tm >> P.p) & 1) ? -1 : P.p;
-                        std::map<int, uint64_t> outside;
-                        for (const DTerm &t : P.terms) {
-                            if (t.wbit < 0) tp.w0 += t.turn;
-                            else if ((Tm >> t.wbit) & 1) tp.wl[local(t.wbit)] += t.turn;
-                            else outside[t.wbit] += t.turn;
-                        }
-                        for (const auto &kv : outside) {
-                            tp.obit[tp.nout] = kv.first;
-                            tp.ow[tp.nout] = kv.second;
-                            ++tp.nout;
-                        }
-                        f.pivots.push_back(tp);
-                        flops += 1.5 * N * double(P.terms.size());
-                    }
+                    if (!diag_tables(op, pass.T, g.S, tg.ns, geo.L, geo.K, a.omask, f.dtab, to))
+                        f.ok = false;
+                    flops += 12.0 * N;
                 } else if (op.kind == TOP_U4) {
                     to.pj = int(std::find(g.S.begin(), g.S.end(), local(op.q0)) - g.S.begin());
                     to.pk = int(std::find(g.S.begin(), g.S.end(), local(op.q1)) - g.S.begin());
@@ -703,19 +789,23 @@ static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, std
         return SV_EUNSUPPORTED;
     }
     Flat f = flatten(s->n, geo, passes);
+    if (!f.ok) {
+        *err = "planner left a diagonal pair term outside the tile";
+        return SV_EUNSUPPORTED;
+    }
 
     const bool c64 = s->dt == SV_C64;
     const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
     const size_t off_groups = 0;
     const size_t off_ops = align_up(off_groups + f.groups.size() * sizeof(TileGroup), 256);
-    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
-    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
+    const size_t off_dtab = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
+    const size_t off_tab = align_up(off_dtab + f.dtab.size() * sizeof(uint64_t), 256);
     const size_t total = off_tab + tab_bytes;
     char *d = nullptr;
     sv_status st = stage_upload(s, total, [&](char *h) {
         std::memcpy(h + off_groups, f.groups.data(), f.groups.size() * sizeof(TileGroup));
         std::memcpy(h + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
-        std::memcpy(h + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
+        std::memcpy(h + off_dtab, f.dtab.data(), f.dtab.size() * sizeof(uint64_t));
         if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + off_tab));
         else fill_phase_table(reinterpret_cast<double2 *>(h + off_tab));
     }, &d, err);
@@ -727,7 +817,7 @@ static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, std
         a.psi = s->psi;
         a.groups = reinterpret_cast<const TileGroup *>(d + off_groups);
         a.ops = reinterpret_cast<const TileOp *>(d + off_ops);
-        a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
+        a.dtab = reinterpret_cast<const uint64_t *>(d + off_dtab);
         a.phase_tab = d + off_tab;
         const int tok = prof_begin(s);
         hipError_t e = launch_tile(a, geo.K, c64, s->stream);
@@ -928,16 +1018,20 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
         return SV_EUNSUPPORTED;
     }
     Flat f = flatten(s->n, geo, passes);
+    if (!f.ok) {
+        *err = "planner left a diagonal pair term outside the tile";
+        return SV_EUNSUPPORTED;
+    }
     const bool c64 = s->dt == SV_C64;
     const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
     const size_t off_ops = align_up(f.groups.size() * sizeof(TileGroup), 256);
-    const size_t off_piv = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
-    const size_t off_tab = align_up(off_piv + f.pivots.size() * sizeof(TilePivot), 256);
+    const size_t off_dtab = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
+    const size_t off_tab = align_up(off_dtab + f.dtab.size() * sizeof(uint64_t), 256);
     const size_t total = off_tab + tab_bytes;
     std::vector<char> h(total);
     std::memcpy(h.data(), f.groups.data(), f.groups.size() * sizeof(TileGroup));
     std::memcpy(h.data() + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
-    std::memcpy(h.data() + off_piv, f.pivots.data(), f.pivots.size() * sizeof(TilePivot));
+    std::memcpy(h.data() + off_dtab, f.dtab.data(), f.dtab.size() * sizeof(uint64_t));
     if (c64) fill_phase_table(reinterpret_cast<float2 *>(h.data() + off_tab));
     else fill_phase_table(reinterpret_cast<double2 *>(h.data() + off_tab));
     sv_plan p = new (std::nothrow) sv_plan_s;
@@ -962,7 +1056,7 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
         a.psi = s->psi;
         a.groups = reinterpret_cast<const TileGroup *>(d);
         a.ops = reinterpret_cast<const TileOp *>(d + off_ops);
-        a.pivots = reinterpret_cast<const TilePivot *>(d + off_piv);
+        a.dtab = reinterpret_cast<const uint64_t *>(d + off_dtab);
         a.phase_tab = d + off_tab;
         p->passes.push_back(a);
     }

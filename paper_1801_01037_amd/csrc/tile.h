@@ -27,36 +27,39 @@ constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
 enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2, TOP_U4 = 3 };
 
 // A diagonal op multiplies each amplitude by e^{2 pi i T / 2^64}, where T is
-// an exact uint64 sum (mod one full turn) over the op's pivots:
-//     T(i) = sum_p [bit p of i is 1] * (w0_p + sum_b [bit b of i is 1] * w_p[b]).
-// Controlled-phase gates with target p and controls b, and one-qubit phases
-// diag(1, e^{i phi}) on p (as w0_p), are all of this form.
-struct TilePivot {
-    int32_t lpivot;        // pivot as a local tile bit, or -1
-    int32_t opivot;        // pivot as a global bit outside the tile, or -1
-    int32_t nout;          // weights on global bits outside the tile
-    int32_t pad;
-    uint64_t w0;
-    uint64_t wl[kTileMaxL];   // weight of each local tile bit
-    int32_t obit[40];         // outside bits with a weight
-    uint64_t ow[40];          // their weights
-};
-constexpr int kTileMaxPivots = 8;
-
+// an exact uint64 sum (mod one full turn): a quadratic form in the index bits,
+//     T(i) = sum_q a_q x_q + sum_{q<q'} Q_qq' x_q x_q'      (x_q = bit q of i).
+// Controlled-phase gates give the Q terms and one-qubit phases
+// diag(1, e^{i phi}) the a terms. The planner never puts a pair term on two
+// qubits outside the tile into a pass. In a group, the tile bits are either
+// register bits S (k < K) or thread bits (the other L-K, fixed by the thread
+// id), and bits outside the tile are fixed by the tile index g, so
+//     T = base(tid, g) + sum_{k in r} coef_k(tid, g) + PR(r)
+// for the register combination r, with
+//     base   = thr[tid][0] + C(g) + sum_{thread bits t set in tid} OW_t(g)
+//     coef_k = thr[tid][1 + k] + OW_{s_k}(g)
+// where thr holds the tile-independent part of each thread, OW_l(g) the
+// weights between tile bit l and the set bits of g, and C(g) the one-qubit
+// phases on bits outside the tile. OW and C are sums of byte-table entries,
+// one per byte of g: tab[(b * (L + 1) + l) * 256 + byte_b(g)] (l = L is C).
+// PR(r), the terms on register bits only, is a constant per op.
 struct TileOp {
     int32_t kind;
     int32_t pj;        // TOP_U / TOP_SWAP: target as a position in the group's S;
-                       // TOP_U4: the lower of its two positions
+                       // TOP_U4: the lower of its two positions;
+                       // TOP_DIAG: 1 if PR is not zero for every r
     int32_t lctrl;     // control as a local tile bit, or -1
     int32_t octrl;     // control as a global index bit outside the tile, or -1
-    int32_t piv0;      // TOP_DIAG: first pivot
-    int32_t npiv;      // TOP_DIAG: number of pivots (<= kTileMaxPivots)
     int32_t pk;        // TOP_U4: the higher of its two positions
-    int32_t pad1;
+    int32_t dthr;      // TOP_DIAG: offset (uint64 units) in the plan's table
+                       // area of thr, 2^(L-K) rows of K+1 values
+    int32_t dout;      // TOP_DIAG: offset of the byte tables, or -1 (none)
+    int32_t dbytes;    // TOP_DIAG: bytes of g the byte tables cover
     double m[8];       // 2x2 in FP64
     float mf[8];       // the same rounded to FP32 (complex64 states)
     double m4[32];     // TOP_U4: 4x4 in FP64, row major, (re, im); basis index
-                       // b0 + 2 b1 with b0 the bit at position pj, b1 at pk
+                       // b0 + 2 b1 with b0 the bit at position pj, b1 at pk.
+                       // TOP_DIAG: e^{2 pi i PR(r) / 2^64}, r < 16, (re, im)
     float mf4[32];     // the same rounded to FP32
 };
 
@@ -70,7 +73,7 @@ struct TileArgs {
     void *psi;
     const TileGroup *groups;
     const TileOp *ops;
-    const TilePivot *pivots;
+    const uint64_t *dtab;          // diagonal-op tables (TileOp.dthr, dout)
     const void *phase_tab;         // e^{2 pi i k/256} then e^{2 pi i k/65536}, k < 256
     uint64_t tmask;                // index bits of the tile (L of them)
     uint64_t omask;                // the other index bits of the register
