@@ -500,9 +500,18 @@ hipError_t launch_k(Kern kern, bool c64, const TileArgs &a, int K, size_t lds, h
 {
     hipError_t e = set_max_lds(kern, c64);
     if (e != hipSuccess) return e;
-    const uint64_t want = uint64_t(cu_count()) * 2;
+    // One work-group per resident slot (LDS and registers decide how many
+    // fit on a CU); each walks its tiles with a grid stride.
+    const int threads = 1 << (a.L - K);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    const uint64_t want = uint64_t(cu_count()) * uint64_t(per_cu);
     const unsigned grid = unsigned(a.ntiles < want ? a.ntiles : want);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(1u << (a.L - K)), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
 
@@ -537,8 +546,8 @@ hipError_t launch_level(const BatchArgs &b, bool c64, int blocks_per_cu, hipStre
     const unsigned grid = ntasks < want ? ntasks : want;
     hipError_t e;
     if (c64) {
-        if ((e = set_max_lds(k_level<true, 512>, true)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_level<true, 512>), dim3(grid), dim3(threads), lds, st, b);
+        if ((e = set_max_lds(k_level<true, 256>, true)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_level<true, 256>), dim3(grid), dim3(threads), lds, st, b);
     } else {
         if ((e = set_max_lds(k_level<false, 256>, false)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_level<false, 256>), dim3(grid), dim3(threads), lds, st, b);

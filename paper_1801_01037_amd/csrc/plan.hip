@@ -224,7 +224,7 @@ TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
     TileGeom g;
     int L = c64 ? kTileL64 : kTileL128;
     int K = c64 ? kTileK64 : kTileK128;
-    int nlow = c64 ? 6 : 5;
+    int nlow = 3;   // 128 B (complex128) or 64 B (complex64) contiguous runs
     // Tuning overrides (bounded to what the kernels are built for).
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));

@@ -18,10 +18,10 @@
 
 namespace svk {
 
-constexpr int kTileMaxL = 13;     // tile bits (c128: 12, c64: 13)
+constexpr int kTileMaxL = 13;     // tile bits (c128 and c64: 12)
 constexpr int kTileMaxK = 4;      // register bits per group
 constexpr int kTileL128 = 12, kTileK128 = 4;   // 64 KiB of complex128 per tile, 256 threads
-constexpr int kTileL64 = 13, kTileK64 = 4;     // 64 KiB of complex64 per tile, 512 threads
+constexpr int kTileL64 = 12, kTileK64 = 4;     // 32 KiB of complex64 per tile, 256 threads
 constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
 
 enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2, TOP_U4 = 3 };

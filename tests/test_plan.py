@@ -111,7 +111,7 @@ def test_fusion_reduces_ops():
     g = qc.layer_circuit(30, 20, 1)
     _, passes, groups, fused_ops = sv.sv_plan_inspect(30, sv.SV_C128, g)
     assert fused_ops < 0.62 * len(g)
-    assert groups < 3 * passes          # light-cone groups fill the register qubits
+    assert groups * 8 < len(g)          # light-cone groups fill the register qubits
 
 
 def test_plan_rejects_bad_gates():
