@@ -224,7 +224,9 @@ TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
     TileGeom g;
     int L = c64 ? kTileL64 : kTileL128;
     int K = c64 ? kTileK64 : kTileK128;
-    int nlow = 3;   // 128 B (complex128) or 64 B (complex64) contiguous runs
+    // Fixed low tile qubits: contiguous runs of one 128 B line, so no line is
+    // shared by two tiles (and fetched twice).
+    int nlow = c64 ? 4 : 3;
     // Tuning overrides (bounded to what the kernels are built for).
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
@@ -580,7 +582,7 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                     to.pk = int(std::find(g.S.begin(), g.S.end(), local(op.q1)) - g.S.begin());
                     std::memcpy(to.m4, op.m4, sizeof to.m4);
                     for (int k = 0; k < 32; ++k) to.mf4[k] = float(op.m4[k]);
-                    flops += 32.0 * N;
+                    flops += 30.0 * N;   // 4 complex products and 3 sums per amplitude
                 } else {
                     const int p = local(op.target);
                     to.pj = int(std::find(g.S.begin(), g.S.end(), p) - g.S.begin());
