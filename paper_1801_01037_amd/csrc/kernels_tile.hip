@@ -167,23 +167,24 @@ template <bool C64, int K, bool SWAP, bool CTRL>
 __device__ __forceinline__ void apply_pair(const Amps<C64, K> &in, Amps<C64, K> &out,
                                            const uint32_t (&li)[1 << K], COp &op)
 {
-    // Every arm writes all of `out`, so the other array's old values are dead
-    // here and the two arrays share no live range.
+    // The planner emits positions below K only; the other arms are unreachable
+    // (an arm that wrote nothing, or copied, would keep the other array live or
+    // be hoisted in front of every op).
     switch (op.pj) {
     case 0: pair_pj<C64, K, 0, SWAP, CTRL>(in, out, li, op); break;
     case 1:
         if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(in, out, li, op);
-        else copy_amps<C64, K>(in, out);
+        else __builtin_unreachable();
         break;
     case 2:
         if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(in, out, li, op);
-        else copy_amps<C64, K>(in, out);
+        else __builtin_unreachable();
         break;
     case 3:
         if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(in, out, li, op);
-        else copy_amps<C64, K>(in, out);
+        else __builtin_unreachable();
         break;
-    default: copy_amps<C64, K>(in, out); break;   // the planner emits no other position
+    default: __builtin_unreachable();
     }
 }
 
@@ -230,7 +231,7 @@ __device__ __forceinline__ void apply_u4(const Amps<C64, K> &in, Amps<C64, K> &o
 #define SV_U4_CASE(P0, P1)                                                        \
     case P0 * 4 + P1:                                                             \
         if constexpr (K > P1) u4_pp<C64, K, P0, P1>(in, out, op);                 \
-        else copy_amps<C64, K>(in, out);                                          \
+        else __builtin_unreachable();                                             \
         break;
     switch (code) {
     SV_U4_CASE(0, 1)
@@ -239,7 +240,7 @@ __device__ __forceinline__ void apply_u4(const Amps<C64, K> &in, Amps<C64, K> &o
     SV_U4_CASE(1, 2)
     SV_U4_CASE(1, 3)
     SV_U4_CASE(2, 3)
-    default: copy_amps<C64, K>(in, out); break;   // the planner emits no other pair
+    default: __builtin_unreachable();   // the planner emits P0 < P1 < K only
     }
 #undef SV_U4_CASE
 }
