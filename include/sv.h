@@ -169,9 +169,12 @@ sv_status sv_synchronize(sv_state s);
  * A plan is a circuit fused into tile passes (as SV_FUSE does) and uploaded to
  * the device once; it stays bound to the state it was made for. A batch runs
  * pass ranges of many plans, on distinct states of one dtype, level by level:
- * launch k applies pass k of every circuit that has one, all their tiles at
- * once, so independent circuits overlap on the device and the launch boundary
- * orders a circuit's passes. */
+ * a level launch applies the next pass of several circuits, all their tiles at
+ * once, so independent circuits overlap on the device, and the launch boundary
+ * orders a circuit's passes (at most one pass of a circuit per level). Levels
+ * take circuits in order of least remaining work (passes left times
+ * amplitudes) up to about two rounds of tasks per resident work-group, so
+ * small circuits finish early and every launch still fills the device. */
 typedef struct sv_plan_s *sv_plan;
 typedef struct sv_batch_s *sv_batch;
 

@@ -1152,6 +1152,19 @@ namespace {
 
 // Builds the level-ordered task list of a batch into `img` (device buffers
 // grown as needed) and queues its upload on `st` through pinned staging.
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
                         const std::vector<int32_t> &first, const std::vector<int32_t> &cnt,
                         hipStream_t st)
@@ -1164,25 +1177,51 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
         pass0[i] = passes.size();
         for (int32_t k = 0; k < cnt[i]; ++k) passes.push_back(plans[i]->passes[first[i] + k]);
     }
+    // Levels by list scheduling, least remaining work first: a level takes the
+    // next pass of circuits in order of remaining work (passes left times
+    // amplitudes) until it holds about two rounds of tasks for every resident
+    // work-group, so each launch fills the GPU while small circuits finish
+    // early instead of waiting for every big circuit's pass at each level.
+    // A circuit has at most one pass per level, so its passes stay in order.
     std::vector<BatchTask> tasks;
     img.level0.clear();
     img.task_circ.clear();
-    int32_t maxc = 0;
-    for (size_t i = 0; i < count; ++i) maxc = std::max(maxc, cnt[i]);
-    for (int32_t lev = 0; lev < maxc; ++lev) {
+    std::vector<uint64_t> amps(count, 0);
+    for (size_t i = 0; i < count; ++i)
+        if (cnt[i] > 0) {
+            const TileArgs &p0 = passes[pass0[i]];
+            amps[i] = p0.ntiles << p0.L;
+        }
+    const uint64_t cap = uint64_t(device_cus()) * uint64_t(std::max(1, b->blocks_per_cu)) *
+                         uint64_t(b->tiles_per_task) * 2 * (uint64_t(1) << 12);
+    std::vector<int32_t> done(count, 0);
+    std::vector<size_t> order;
+    order.reserve(count);
+    for (;;) {
+        order.clear();
+        for (size_t i = 0; i < count; ++i)
+            if (done[i] < cnt[i]) order.push_back(i);
+        if (order.empty()) break;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return uint64_t(cnt[x] - done[x]) * amps[x] < uint64_t(cnt[y] - done[y]) * amps[y];
+        });
         img.level0.push_back(uint32_t(tasks.size()));
-        for (size_t i = 0; i < count; ++i) {
-            if (lev >= cnt[i]) continue;
-            const uint64_t nt = passes[pass0[i] + lev].ntiles;
+        uint64_t level_amps = 0;
+        for (size_t i : order) {
+            if (level_amps >= cap) break;
+            const int32_t pi = int32_t(pass0[i]) + done[i];
+            const uint64_t nt = passes[pi].ntiles;
             for (uint64_t t0 = 0; t0 < nt; t0 += b->tiles_per_task) {
                 BatchTask t;
-                t.pass = int32_t(pass0[i] + lev);
+                t.pass = pi;
                 t.circ = int32_t(i);
                 t.tile0 = uint32_t(t0);
                 t.ntiles = uint32_t(std::min<uint64_t>(b->tiles_per_task, nt - t0));
                 tasks.push_back(t);
                 img.task_circ.push_back(int32_t(i));
             }
+            level_amps += amps[i];
+            ++done[i];
         }
     }
     img.level0.push_back(uint32_t(tasks.size()));

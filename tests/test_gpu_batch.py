@@ -1,5 +1,5 @@
-"""GPU: many circuits in one persistent launch (sv_batch_run) give the same
-result as each circuit run alone, and match the oracle."""
+"""GPU: many circuits run as one batch (sv_batch_run, level launches) give the
+same result as each circuit run alone, and match the oracle."""
 import numpy as np
 import pytest
 
@@ -43,6 +43,31 @@ def test_batch_of_full_tiles():
             sv.sv_plan_destroy(p)
         for h in states:
             sv.sv_destroy(h)
+    for (n, d, s), g, got in zip(specs, circuits, outs):
+        assert np.array_equal(got, _run_alone(n, dtype, g)), (n, d)
+
+
+def test_small_circuits_finish_before_a_large_one():
+    """Levels take the circuits with the least remaining work first: sixteen
+    10-qubit circuits end before one 22-qubit circuit of the same batch, and
+    every result equals the circuit run alone."""
+    dtype = sv.SV_C64
+    specs = [(22, 30, 901)] + [(10, 12, 910 + i) for i in range(16)]
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_run(b, plans)
+        start, end = sv.sv_batch_times(b, len(plans))
+        outs = [sv.sv_copy_out(h) for h in states]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    assert max(end[1:]) < end[0], (end[0], max(end[1:]))
     for (n, d, s), g, got in zip(specs, circuits, outs):
         assert np.array_equal(got, _run_alone(n, dtype, g)), (n, d)
 
