@@ -26,6 +26,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # flop/clock/CU (the FP32 figure counts packed FMA; without packed math the
 # FP32 rate equals the FP64 one).
 ALU_PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}
+# Dense MFMA peaks (FP64 and FP32 matrix instructions): the compute roof of the
+# dense-block kernel.
+MFMA_PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}
 WORKLOAD_N = 30
 PROBS_COUNT = 1 << 20
 
@@ -40,8 +43,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate"], default="fused",
-                    help="fused: SV_FUSE tile passes; pergate: one launch per gate")
+    ap.add_argument("--mode", choices=["fused", "pergate", "dense"], default="fused",
+                    help="fused: SV_FUSE tile passes; pergate: one launch per gate; "
+                         "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -145,13 +149,14 @@ def roofline(prof, dtype_tag):
     avg_ms = d["total_ms"] / d["launches"]
     per_launch = d["bytes"] / d["launches"]
     flops = d["flops"] / d["launches"]
-    alu_peak = ALU_PEAK_TFLOPS[dtype_tag]
+    mfma = cls == "dense"
+    alu_peak = (MFMA_PEAK_TFLOPS if mfma else ALU_PEAK_TFLOPS)[dtype_tag]
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4)}
     alu_ach = flops / (avg_ms * 1e-3) / 1e12
-    alu = {"bound": "alu", "achieved": round(alu_ach, 2), "peak": alu_peak, "unit": "TFLOP/s",
-           "frac": round(alu_ach / alu_peak, 4)}
+    alu = {"bound": "mfma" if mfma else "alu", "achieved": round(alu_ach, 2), "peak": alu_peak,
+           "unit": "TFLOP/s", "frac": round(alu_ach / alu_peak, 4)}
     t_hbm = per_launch / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (alu_peak * 1e12)
     first, second = (alu, hbm) if t_alu > t_hbm else (hbm, alu)
@@ -274,7 +279,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
         del src, dst
-    flags = sv.SV_FUSE if args.mode == "fused" else 0
+    flags = {"fused": sv.SV_FUSE, "pergate": 0, "dense": sv.SV_FUSE_DENSE}[args.mode]
     n = args.qubits
     log(f"[bench] c128 n={n} mode={args.mode} steps={args.steps} warmup={args.warmup}")
     r128 = run_dtype(sv, torch, sv.SV_C128, n, args.steps, args.warmup, flags)
