@@ -36,6 +36,7 @@ def load(path: str):
     L.orc_apply_ctrl.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
     L.orc_apply_cphase.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_double]
+    L.orc_apply_mcu.argtypes = [dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, dp]
     L.orc_run_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
     L.orc_run_circuit.restype = ctypes.c_int
     L.orc_probs.argtypes = [dp, ctypes.c_uint64, ctypes.c_uint64, dp]
@@ -84,6 +85,16 @@ def apply_ctrl(psi: np.ndarray, c: int, t: int, m) -> None:
     n = _check_state(psi)
     m = np.ascontiguousarray(m, dtype=np.float64)
     lib().orc_apply_ctrl(_dp(psi.view(np.float64)), n, c, t, _dp(m))
+
+
+def apply_mcu(psi: np.ndarray, controls, t: int, m) -> None:
+    """2x2 gate on qubit t, applied where every qubit in `controls` is 1."""
+    n = _check_state(psi)
+    mask = 0
+    for c in controls:
+        mask |= 1 << int(c)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    lib().orc_apply_mcu(_dp(psi.view(np.float64)), n, mask, t, _dp(m))
 
 
 def apply_cphase(psi: np.ndarray, c: int, t: int, theta: float) -> None:

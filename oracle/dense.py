@@ -11,7 +11,9 @@ Index convention: qubit q is bit q of the amplitude index, so the operator of
 Q on qubit t is I_{2^(n-1-t)} (x) Q (x) I_{2^t} (the most significant qubit is
 the leftmost Kronecker factor). A controlled gate is
 P0_c (x) I  +  P1_c (x) Q_t  (projectors on the control bit, identities
-elsewhere), which acts with Q only where bit c is one (caption of Algorithm 1).
+elsewhere), which acts with Q only where bit c is one (caption of Algorithm 1);
+with several controls (the Toffoli gate of section Quantum Circuits is X with
+two) the projectors of all of them multiply.
 """
 from __future__ import annotations
 
@@ -45,6 +47,13 @@ def operator_ctrl(n: int, c: int, t: int, q: np.ndarray) -> np.ndarray:
     return _kron_chain({c: _P0}, n) + _kron_chain({c: _P1, t: q}, n)
 
 
+def operator_mcu(n: int, controls, t: int, q: np.ndarray) -> np.ndarray:
+    """Q on t where every control qubit is one: I + (P1 on each control) (x) (Q - I)_t."""
+    factors = {int(c): _P1 for c in controls}
+    factors[t] = q - _I2
+    return np.eye(2 ** n, dtype=np.complex128) + _kron_chain(factors, n)
+
+
 def operator_cphase(n: int, c: int, t: int, theta: float) -> np.ndarray:
     return operator_ctrl(n, c, t, np.diag([1.0, np.exp(1j * theta)]))
 
@@ -57,6 +66,11 @@ def gate_operator(n: int, g) -> np.ndarray:
         return operator_ctrl(n, c, t, matrix_of(g["m"]))
     if kind == 2:
         return operator_cphase(n, c, t, float(g["m"][0]))
+    if kind == 3:
+        lo = int(np.array(g["control"], dtype=np.int32).view(np.uint32))
+        hi = int(np.array(g["flags"], dtype=np.int32).view(np.uint32))
+        mask = lo | (hi << 32)
+        return operator_mcu(n, [q for q in range(n) if (mask >> q) & 1], t, matrix_of(g["m"]))
     raise ValueError(f"unknown gate kind {kind}")
 
 

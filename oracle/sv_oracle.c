@@ -19,7 +19,10 @@
  *     loop over the 2^i pairs of a block;
  *   - a gate with control c and target t runs the same update only on
  *     amplitudes whose index has bit c set (the caption of Algorithm 1);
- *   - controlled-phase is the controlled gate with Q = diag(1, e^{i theta}).
+ *   - controlled-phase is the controlled gate with Q = diag(1, e^{i theta});
+ *   - a gate with several controls (the Toffoli, or controlled-controlled-NOT,
+ *     gate of section Quantum Circuits is X with two) updates only where every
+ *     control bit is set.
  *
  * Arithmetic: every complex product is written out in real arithmetic and the
  * file is built with -ffp-contract=off, so each operation rounds once.
@@ -33,14 +36,15 @@
 
 /* Gate record as stored in the serialized gate lists (80 bytes). */
 typedef struct {
-    int32_t kind;     /* 0: 2x2 on target; 1: controlled 2x2; 2: controlled phase */
-    int32_t control;  /* -1 when none */
+    int32_t kind;     /* 0: 2x2 on target; 1: controlled 2x2; 2: controlled phase;
+                         3: 2x2 with a set of controls */
+    int32_t control;  /* -1 when none; kind 3: low 32 bits of the control mask */
     int32_t target;
-    int32_t flags;
+    int32_t flags;    /* kind 3: high 32 bits of the control mask */
     double m[8];      /* q11, q12, q21, q22 as (re, im); kind 2: m[0] = theta */
 } orc_gate;
 
-enum { ORC_U = 0, ORC_CU = 1, ORC_CPHASE = 2 };
+enum { ORC_U = 0, ORC_CU = 1, ORC_CPHASE = 2, ORC_MCU = 3 };
 
 /* psi is interleaved (re, im) doubles, 2^n complex entries. */
 
@@ -92,6 +96,18 @@ void orc_apply_ctrl(double *psi, int n, int c, int t, const double m[8])
                 pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
 }
 
+/* Algorithm 1 with a set of controls (bit mask cmask, not holding t): the
+ * same loops, updating only where every control bit of the index is one. */
+void orc_apply_mcu(double *psi, int n, uint64_t cmask, int t, const double m[8])
+{
+    uint64_t N = (uint64_t)1 << n;
+    uint64_t stride = (uint64_t)1 << t;
+    for (uint64_t j = 0; j < N; j += 2 * stride)
+        for (uint64_t k = j; k < j + stride; ++k)
+            if ((k & cmask) == cmask)
+                pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
+}
+
 /* Controlled phase: the controlled gate with Q = diag(1, e^{i theta}). */
 void orc_apply_cphase(double *psi, int n, int c, int t, double theta)
 {
@@ -120,6 +136,14 @@ int orc_run_circuit(double *psi, int n, const orc_gate *g, size_t count)
                 return -1;
             orc_apply_cphase(psi, n, c, t, g[i].m[0]);
             break;
+        case ORC_MCU: {
+            uint64_t cm = (uint64_t)(uint32_t)g[i].control |
+                          ((uint64_t)(uint32_t)g[i].flags << 32);
+            if ((cm >> t) & 1 || (n < 64 && (cm >> n) != 0))
+                return -1;
+            orc_apply_mcu(psi, n, cm, t, g[i].m);
+            break;
+        }
         default:
             return -1;
         }

@@ -32,6 +32,8 @@ import numpy as np
 G_U = 0        # 2x2 unitary on `target`
 G_CU = 1       # 2x2 unitary on `target`, applied where bit `control` is 1
 G_CPHASE = 2   # diag(1, e^{i theta}) on `target`, controlled by `control`
+G_MCU = 3      # 2x2 unitary on `target`, applied where every control bit is 1;
+               # the control mask's low 32 bits are in `control`, high 32 in `flags`
 
 GATE_DTYPE = np.dtype([
     ("kind", "<i4"), ("control", "<i4"), ("target", "<i4"), ("flags", "<i4"),
@@ -118,6 +120,30 @@ def gate_cu(control: int, target: int, m) -> np.ndarray:
 
 def gate_cnot(control: int, target: int) -> np.ndarray:
     return gate_cu(control, target, X_MATRIX)
+
+
+def gate_mcu(controls, target: int, m) -> np.ndarray:
+    """A 2x2 gate with a set of controls (Toffoli: gate_mcu((a, b), t, X_MATRIX))."""
+    mask = 0
+    for c in controls:
+        mask |= 1 << int(c)
+    g = np.zeros(1, GATE_DTYPE)
+    g["kind"], g["target"] = G_MCU, target
+    g["control"] = np.array(mask & 0xFFFFFFFF, dtype=np.uint32).view(np.int32)
+    g["flags"] = np.array(mask >> 32, dtype=np.uint32).view(np.int32)
+    g["m"][0] = m
+    return g
+
+
+def gate_control_mask(g) -> int:
+    """The control qubits of a record as a bit mask (0 for none)."""
+    kind = int(g["kind"])
+    if kind == G_MCU:
+        lo = int(np.array(g["control"], dtype=np.int32).view(np.uint32))
+        hi = int(np.array(g["flags"], dtype=np.int32).view(np.uint32))
+        return lo | (hi << 32)
+    c = int(g["control"])
+    return 0 if c < 0 else 1 << c
 
 
 def gate_cphase(control: int, target: int, theta: float) -> np.ndarray:
@@ -219,10 +245,10 @@ def workload_layers_qft(n: int = 16, depth: int = 100, seed: int = 0) -> np.ndar
 
 
 def gate_qubits(g) -> tuple:
-    """Qubits a gate record touches (control first when present)."""
-    if int(g["control"]) >= 0:
-        return (int(g["control"]), int(g["target"]))
-    return (int(g["target"]),)
+    """Qubits a gate record touches (controls first, ascending)."""
+    mask = gate_control_mask(g)
+    ctrl = tuple(q for q in range(64) if (mask >> q) & 1)
+    return ctrl + (int(g["target"]),)
 
 
 def random_state(n: int, seed: int) -> np.ndarray:

@@ -26,6 +26,7 @@ MUTANTS = {
     "conjugated_phase": [("cos(theta), sin(theta)", "cos(theta), -sin(theta)")],
     "qft_no_bit_reversal": [("<< (n - 1 - b);", "<< b;")],
     "norm_drops_imag": [("+ psi[2 * i + 1] * psi[2 * i + 1];", ";")],
+    "mcu_any_control": [("if ((k & cmask) == cmask)", "if (k & cmask)")],
 }
 
 PINS = [
@@ -40,6 +41,8 @@ PINS = [
     pins.test_product_state_rule,
     pins.test_norm_and_probs_against_exact_sums,
     pins.test_controlled_gate_leaves_control_zero_half_untouched,
+    pins.test_toffoli_truth_table,
+    lambda: pins.test_mcu_stride_tier_matches_dense_tier((0, 2, 4), 5),
 ]
 
 
