@@ -59,13 +59,16 @@ enum {
     SV_G_U = 0,       /* 2x2 matrix m on `target`; `control` must be -1            */
     SV_G_CU = 1,      /* 2x2 matrix m on `target` where bit `control` is 1 (CNOT:  */
                       /* m = X)                                                    */
-    SV_G_CPHASE = 2   /* diag(1, e^{i theta}) on `target` where bit `control` is 1; */
+    SV_G_CPHASE = 2,  /* diag(1, e^{i theta}) on `target` where bit `control` is 1; */
                       /* theta = m[0] in radians (controlled-phase R_k has         */
                       /* theta = 2 pi / 2^k)                                       */
+    SV_G_MCU = 3      /* 2x2 matrix m on `target` where every bit of a control     */
+                      /* mask is 1 (Toffoli: two controls, m = X); the mask's low  */
+                      /* 32 bits are in `control`, its high 32 bits in `flags`    */
 };
 
 /* One gate of a circuit: 80 bytes, the same record the seeded generators
- * write. `flags` is reserved and must be 0. */
+ * write. `flags` must be 0 except for SV_G_MCU. */
 typedef struct {
     int32_t kind;
     int32_t control;    /* -1 when the gate has no control */
@@ -128,6 +131,13 @@ sv_status sv_apply_1q(sv_state s, int target, const double m[8]);
  * (caption of Algorithm 1). control != target. CNOT is m = X; a controlled
  * phase is m = diag(1, e^{i theta}). */
 sv_status sv_apply_ctrl(sv_state s, int control, int target, const double m[8]);
+
+/* Applies m to `target` on the amplitudes whose index has every bit of
+ * control_mask set: the controlled update with several controls (the Toffoli,
+ * or controlled-controlled-NOT, gate of section Quantum Circuits is m = X with
+ * two). control_mask must be non-zero, below 2^n and must not hold `target`.
+ * One pass over the amplitudes whose control bits are all set. */
+sv_status sv_apply_mcu(sv_state s, uint64_t control_mask, int target, const double m[8]);
 
 /* Controlled phase diag(1, e^{i theta}) on (control, target); symmetric in the
  * two qubits. The phase e^{i theta} is formed in FP64 for both dtypes. */

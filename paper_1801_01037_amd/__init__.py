@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
-    "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_cphase",
+    "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
@@ -73,6 +73,7 @@ _SIGNATURES = {
     "sv_reset": ([_vp, _u64], _int),
     "sv_apply_1q": ([_vp, _int, _dp], _int),
     "sv_apply_ctrl": ([_vp, _int, _int, _dp], _int),
+    "sv_apply_mcu": ([_vp, ctypes.c_uint64, _int, _dp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
     "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
     "sv_probs": ([_vp, _u64, _u64, _dp], _int),
@@ -180,6 +181,15 @@ def sv_apply_1q(h: int, target: int, m) -> None:
 
 def sv_apply_ctrl(h: int, control: int, target: int, m) -> None:
     _check(lib().sv_apply_ctrl(h, control, target, _mat(m)))
+
+
+def sv_apply_mcu(h: int, controls, target: int, m) -> None:
+    """2x2 gate on `target` where every qubit of `controls` is 1 (Toffoli:
+    two controls, m = X)."""
+    mask = 0
+    for c in controls:
+        mask |= 1 << int(c)
+    _check(lib().sv_apply_mcu(h, mask, target, _mat(m)))
 
 
 def sv_apply_cphase(h: int, control: int, target: int, theta: float) -> None:
@@ -357,6 +367,9 @@ class StateVector:
 
     def apply_ctrl(self, control, target, m):
         sv_apply_ctrl(self.handle, control, target, m)
+
+    def apply_mcu(self, controls, target, m):
+        sv_apply_mcu(self.handle, controls, target, m)
 
     def apply_cphase(self, control, target, theta):
         sv_apply_cphase(self.handle, control, target, theta)

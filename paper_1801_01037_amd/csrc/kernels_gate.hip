@@ -4,9 +4,10 @@
 // The pair update is the stride rule of State Vector Partitioning: for a gate
 // on qubit t every pair (i0, i0 + 2^t) with bit t of i0 clear becomes
 // (q11 a + q12 b, q21 a + q22 b); a control c restricts it to indices with bit
-// c set (caption of Algorithm 1). Instead of the paper's two nested loops, a
+// c set (caption of Algorithm 1), several controls (a Toffoli gate has two) to
+// indices with all of them set. Instead of the paper's two nested loops, a
 // flat work index is expanded by inserting the fixed bits (target = 0,
-// control = 1), so consecutive lanes touch consecutive 16-byte chunks of both
+// controls = 1), so consecutive lanes touch consecutive 16-byte chunks of both
 // halves of every pair and both streams are coalesced for any t.
 #include <type_traits>
 
@@ -59,10 +60,10 @@ struct PairArgs {
     void *psi;
     uint64_t items;       // work items (chunk pairs, or chunks for kInChunk)
     uint64_t tstride;     // 2^t in amplitudes
-    int nins;             // fixed index bits to insert (0..2), ascending
-    int pos0, pos1;
-    uint64_t val0, val1;
+    int nins;             // fixed index bits to insert, ascending positions
+    uint64_t vals;        // bit k: the value inserted at pos[k]
     CMat<R> m;
+    uint8_t pos[64];
 };
 
 template <bool C64, int LAYOUT, bool SWAP, int U>
@@ -80,8 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs<std::conditional_t<C64
     for (int u = 0; u < U; ++u) {
         const uint64_t item = first + uint64_t(u) * kBlock;
         uint64_t x = item * E;
-        if (a.nins > 0) x = insert_bit(x, a.pos0, a.val0);
-        if (a.nins > 1) x = insert_bit(x, a.pos1, a.val1);
+        for (int k = 0; k < a.nins; ++k) x = insert_bit(x, a.pos[k], (a.vals >> k) & 1u);
         ca[u] = x / E;
         cb[u] = (x + a.tstride) / E;
         if (item < a.items) {
@@ -252,7 +252,7 @@ hipError_t launch_pair_t(const PairArgs<std::conditional_t<C64, float, double>> 
 }
 
 template <bool C64>
-hipError_t launch_pair_p(void *psi, int n, int t, int c, const Mat2 &m, bool swap_only,
+hipError_t launch_pair_p(void *psi, int n, int t, uint64_t cmask, const Mat2 &m, bool swap_only,
                          hipStream_t st)
 {
     using R = std::conditional_t<C64, float, double>;
@@ -262,31 +262,25 @@ hipError_t launch_pair_p(void *psi, int n, int t, int c, const Mat2 &m, bool swa
     a.tstride = uint64_t(1) << t;
     a.m = to_cmat<R>(m);
     // Fixed bits inserted into the work index, ascending: the target bit (0)
-    // when the pair spans two chunks, the control bit (1) when it is constant
-    // over a chunk.
-    int pos[2], nins = 0;
-    uint64_t val[2];
+    // when the pair spans two chunks, every control bit (1) that is constant
+    // over a chunk. A complex64 control on bit 0 selects the odd amplitude of
+    // each chunk instead (kSplitOdd).
     int layout;
     if (t >= lgE) {
-        layout = (c >= 0 && c < lgE) ? kSplitOdd : kSplit;
+        layout = (lgE > 0 && (cmask & 1u)) ? kSplitOdd : kSplit;
     } else {
         layout = kInChunk;
     }
-    auto add = [&](int p_, uint64_t v_) { pos[nins] = p_; val[nins] = v_; ++nins; };
-    const bool ins_t = layout != kInChunk;
-    const bool ins_c = c >= lgE;
-    if (ins_t && ins_c) {
-        if (t < c) { add(t, 0); add(c, 1); } else { add(c, 1); add(t, 0); }
-    } else if (ins_t) {
-        add(t, 0);
-    } else if (ins_c) {
-        add(c, 1);
+    const uint64_t ins_mask = (layout != kInChunk ? (uint64_t(1) << t) : 0) |
+                              (cmask & ~((uint64_t(1) << lgE) - 1));
+    int nins = 0;
+    for (int b = 0; b < 64; ++b) {
+        if (!((ins_mask >> b) & 1)) continue;
+        a.pos[nins] = uint8_t(b);
+        if (b != t) a.vals |= uint64_t(1) << nins;   // a control: 1; the target: 0
+        ++nins;
     }
     a.nins = nins;
-    a.pos0 = nins > 0 ? pos[0] : 0;
-    a.val0 = nins > 0 ? val[0] : 0;
-    a.pos1 = nins > 1 ? pos[1] : 0;
-    a.val1 = nins > 1 ? val[1] : 0;
     a.items = (uint64_t(1) << n) >> (lgE + nins);
     if (layout == kSplit)
         return swap_only ? launch_pair_t<C64, kSplit, true>(a, st)
@@ -314,11 +308,11 @@ hipError_t launch_init(void *psi, int n, sv_dtype dt, uint64_t basis, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_pair(void *psi, int n, sv_dtype dt, int t, int c, const Mat2 &m,
+hipError_t launch_pair(void *psi, int n, sv_dtype dt, int t, uint64_t cmask, const Mat2 &m,
                        bool swap_only, hipStream_t st)
 {
-    return dt == SV_C64 ? launch_pair_p<true>(psi, n, t, c, m, swap_only, st)
-                        : launch_pair_p<false>(psi, n, t, c, m, swap_only, st);
+    return dt == SV_C64 ? launch_pair_p<true>(psi, n, t, cmask, m, swap_only, st)
+                        : launch_pair_p<false>(psi, n, t, cmask, m, swap_only, st);
 }
 
 hipError_t launch_diag(void *psi, int n, sv_dtype dt, const DiagTerm *terms, int count,

@@ -82,6 +82,25 @@ sv_status make_handle(void *psi, int n, sv_dtype dt, void *stream, bool owned, s
     return SV_OK;
 }
 
+// Planned circuits (tile and dense plans) hold gates with at most one control.
+sv_status reject_mcu(const sv_gate *gates, size_t n_gates)
+{
+    for (size_t i = 0; i < n_gates; ++i)
+        if (gates[i].kind == SV_G_MCU)
+            return fail(SV_EUNSUPPORTED,
+                        "gate %zu: plans do not hold gates with several controls "
+                        "(sv_run_circuit and sv_apply_mcu apply them)", i);
+    return SV_OK;
+}
+
+// The control qubits of a (validated) gate record as a bit mask.
+uint64_t control_mask(const sv_gate &g)
+{
+    if (g.kind == SV_G_MCU)
+        return uint64_t(uint32_t(g.control)) | (uint64_t(uint32_t(g.flags)) << 32);
+    return g.kind == SV_G_U ? 0 : uint64_t(1) << g.control;
+}
+
 // Queues one gate as its own kernel (one pass over the touched amplitudes).
 sv_status queue_gate(sv_state s, const sv_gate &g)
 {
@@ -89,15 +108,19 @@ sv_status queue_gate(sv_state s, const sv_gate &g)
     std::memcpy(m.q, g.m, sizeof m.q);
     const double N = std::ldexp(1.0, s->n), sb = svk::elem_bytes(s->dt);
     const uint64_t tbit = uint64_t(1) << g.target;
-    const uint64_t both = g.kind == SV_G_U ? tbit : tbit | (uint64_t(1) << g.control);
-    const bool ctrl = g.kind != SV_G_U;
+    const uint64_t cm = control_mask(g);
+    const uint64_t both = tbit | cm;
+    const bool ctrl = cm != 0;
+    const int nc = __builtin_popcountll(cm);
     // Kind of kernel, and the amplitudes it must read and write.
     enum { PAIR, SWAP, DIAG } how;
     if (g.kind == SV_G_CPHASE) how = DIAG;
     else if (svk::is_pauli_x(g.m)) how = SWAP;
     else if (svk::is_phase_diag(g.m)) how = DIAG;
     else how = PAIR;
-    const double touched = how == DIAG ? (ctrl ? N / 4 : N / 2) : (ctrl ? N / 2 : N);
+    // amplitudes updated: those with every control set (and, for a phase, the
+    // target set too)
+    const double touched = std::ldexp(N, -(nc + (how == DIAG ? 1 : 0)));
     int cls;
     double flops;
     if (how == PAIR) { cls = ctrl ? svk::KC_PAIR_CTRL : svk::KC_PAIR; flops = 14 * touched; }
@@ -107,8 +130,7 @@ sv_status queue_gate(sv_state s, const sv_gate &g)
     const int tok = svk::prof_begin(s);
     hipError_t e;
     if (how == PAIR || how == SWAP) {
-        e = svk::launch_pair(s->psi, s->n, s->dt, g.target, ctrl ? g.control : -1, m,
-                             how == SWAP, s->stream);
+        e = svk::launch_pair(s->psi, s->n, s->dt, g.target, cm, m, how == SWAP, s->stream);
     } else {
         const double theta = g.kind == SV_G_CPHASE ? g.m[0] : std::atan2(g.m[7], g.m[6]);
         svk::DiagTerm t{both, both, svk::angle_to_turn(theta)};
@@ -121,7 +143,7 @@ sv_status queue_gate(sv_state s, const sv_gate &g)
 
 sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
 {
-    if (g.flags != 0) return fail(SV_EINVAL, "gate %zu: flags must be 0", idx);
+    if (g.flags != 0 && g.kind != SV_G_MCU) return fail(SV_EINVAL, "gate %zu: flags must be 0", idx);
     if (g.target < 0 || g.target >= s->n)
         return fail(SV_EINVAL, "gate %zu: target %d out of range [0, %d)", idx, g.target, s->n);
     switch (g.kind) {
@@ -135,6 +157,15 @@ sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
         if (g.control == g.target)
             return fail(SV_EINVAL, "gate %zu: control equals target (%d)", idx, g.target);
         break;
+    case SV_G_MCU: {
+        const uint64_t cm = control_mask(g);
+        if (cm == 0) return fail(SV_EINVAL, "gate %zu: SV_G_MCU needs at least one control", idx);
+        if (s->n < 64 && (cm >> s->n) != 0)
+            return fail(SV_EINVAL, "gate %zu: control mask has a bit at or above n = %d", idx, s->n);
+        if ((cm >> g.target) & 1)
+            return fail(SV_EINVAL, "gate %zu: control mask holds the target (%d)", idx, g.target);
+        break;
+    }
     default:
         return fail(SV_EINVAL, "gate %zu: unknown kind %d", idx, g.kind);
     }
@@ -184,7 +215,7 @@ bool is_phase_diag(const double m[8])
 
 extern "C" {
 
-int sv_version(void) { return 1; }
+int sv_version(void) { return 2; }
 
 const char *sv_last_error(void) { return g_err.c_str(); }
 
@@ -294,6 +325,18 @@ sv_status sv_apply_ctrl(sv_state s, int control, int target, const double m[8])
     return queue_gate(s, g);
 }
 
+sv_status sv_apply_mcu(sv_state s, uint64_t control_mask, int target, const double m[8])
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!m) return fail(SV_EINVAL, "null matrix");
+    sv_gate g{SV_G_MCU, int32_t(uint32_t(control_mask)), target,
+              int32_t(uint32_t(control_mask >> 32)), {}};
+    std::memcpy(g.m, m, sizeof g.m);
+    if (sv_status st = validate_gate(s, g, 0)) return st;
+    DeviceScope ds(s->device);
+    return queue_gate(s, g);
+}
+
 sv_status sv_apply_cphase(sv_state s, int control, int target, double theta)
 {
     if (sv_status st = check_handle(s)) return st;
@@ -315,9 +358,22 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
         if (sv_status st = validate_gate(s, gates[i], i)) return st;
     DeviceScope ds(s->device);
     if (flags & (SV_FUSE | SV_FUSE_DENSE | SV_GRAPH)) {
-        std::string err;
-        sv_status st = svk::plan_run(s, gates, n_gates, flags, &err);
-        if (st != SV_OK) return fail(st, "%s", err.c_str());
+        // Gates with several controls run as their own launches between the
+        // planned segments of the other gates (list order is kept).
+        size_t i = 0;
+        while (i < n_gates) {
+            if (gates[i].kind == SV_G_MCU) {
+                if (sv_status st = queue_gate(s, gates[i])) return st;
+                ++i;
+                continue;
+            }
+            size_t j = i;
+            while (j < n_gates && gates[j].kind != SV_G_MCU) ++j;
+            std::string err;
+            sv_status st = svk::plan_run(s, gates + i, j - i, flags, &err);
+            if (st != SV_OK) return fail(st, "%s", err.c_str());
+            i = j;
+        }
         return SV_OK;
     }
     for (size_t i = 0; i < n_gates; ++i)
@@ -437,6 +493,7 @@ sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, si
     probe.dt = dtype;
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
+    if (sv_status st = reject_mcu(gates, n_gates)) return st;
     if (svk::plan_inspect(n_qubits, dtype, gates, n_gates, gate_op, n_passes, n_groups, n_ops) != 0)
         return fail(SV_EUNSUPPORTED, "planner could not place every gate with this tile geometry");
     return SV_OK;
@@ -453,6 +510,7 @@ sv_status sv_plan_dense_inspect(int n_qubits, const sv_gate *gates, size_t n_gat
     probe.n = n_qubits;
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
+    if (sv_status st = reject_mcu(gates, n_gates)) return st;
     const int nb = svk::plan_dense_inspect(n_qubits, gates, n_gates, block_masks, block_mats, cap);
     if (n_blocks) *n_blocks = nb;
     return SV_OK;
@@ -466,6 +524,7 @@ sv_status sv_plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_pl
     if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(s, gates[i], i)) return st;
+    if (sv_status st = reject_mcu(gates, n_gates)) return st;
     DeviceScope ds(s->device);
     std::string err;
     sv_status st = svk::plan_create(s, gates, n_gates, out, &err);

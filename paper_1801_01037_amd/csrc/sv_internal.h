@@ -37,7 +37,7 @@ constexpr int kMaxDiagTerms = 64;
 hipError_t launch_init(void *psi, int n, sv_dtype dt, uint64_t basis, hipStream_t st);
 // 2x2 on target t, optionally controlled by c (c < 0: none). swap_only: the
 // matrix is X (a pure exchange of the two amplitudes).
-hipError_t launch_pair(void *psi, int n, sv_dtype dt, int t, int c, const Mat2 &m,
+hipError_t launch_pair(void *psi, int n, sv_dtype dt, int t, uint64_t cmask, const Mat2 &m,
                        bool swap_only, hipStream_t st);
 // Product of the diagonal terms (at most kMaxDiagTerms).
 hipError_t launch_diag(void *psi, int n, sv_dtype dt, const DiagTerm *terms, int count,

@@ -119,3 +119,17 @@ def test_plan_rejects_bad_gates():
         sv.sv_plan_inspect(4, sv.SV_C128, qc.gate_cnot(2, 2))
     with pytest.raises(sv.SVError):
         sv.sv_plan_inspect(4, sv.SV_C128, qc.gate_u(4, qc.X_MATRIX))
+
+
+def test_plans_reject_gates_with_several_controls():
+    toffoli = qc.gate_mcu((0, 1), 2, qc.X_MATRIX)
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_inspect(6, sv.SV_C128, np.concatenate([qc.gate_u(0, qc.H_MATRIX), toffoli]))
+    assert e.value.status == sv.SV_EUNSUPPORTED
+    # malformed masks are argument errors: the target among the controls, a
+    # control at or above n, no control at all
+    for bad in (qc.gate_mcu((0, 2), 2, qc.X_MATRIX), qc.gate_mcu((0, 6), 2, qc.X_MATRIX),
+                qc.gate_mcu((), 2, qc.X_MATRIX)):
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_plan_inspect(6, sv.SV_C128, bad)
+        assert e.value.status == sv.SV_EINVAL
