@@ -111,16 +111,20 @@ sv_status queue_gate(sv_state s, const sv_gate &g)
     const uint64_t cm = control_mask(g);
     const uint64_t both = tbit | cm;
     const bool ctrl = cm != 0;
-    const int nc = __builtin_popcountll(cm);
     // Kind of kernel, and the amplitudes it must read and write.
     enum { PAIR, SWAP, DIAG } how;
     if (g.kind == SV_G_CPHASE) how = DIAG;
     else if (svk::is_pauli_x(g.m)) how = SWAP;
     else if (svk::is_phase_diag(g.m)) how = DIAG;
     else how = PAIR;
-    // amplitudes updated: those with every control set (and, for a phase, the
-    // target set too)
-    const double touched = std::ldexp(N, -(nc + (how == DIAG ? 1 : 0)));
+    // Amplitudes whose 128-byte lines the kernel must read and write: only a
+    // control (or, for a phase, the target) on a bit that selects whole lines
+    // (bit >= 3 for complex128, >= 4 for complex64) halves the lines touched.
+    const int line_bit = s->dt == SV_C64 ? 4 : 3;
+    const uint64_t line_sel = ~((uint64_t(1) << line_bit) - 1);
+    const int nsel = __builtin_popcountll(cm & line_sel) +
+                     ((how == DIAG && (tbit & line_sel)) ? 1 : 0);
+    const double touched = std::ldexp(N, -nsel);
     int cls;
     double flops;
     if (how == PAIR) { cls = ctrl ? svk::KC_PAIR_CTRL : svk::KC_PAIR; flops = 14 * touched; }
