@@ -167,6 +167,21 @@ def product_state_amplitude(vectors: np.ndarray, index: int) -> complex:
     return amp
 
 
+def sample_indices(psi: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Measurement by inverting the CDF (the measurement of section Quantum
+    Circuits: index j with probability |alpha_j|^2 / norm): for each u in
+    [0, 1), the first j with CDF(j) > u * norm, CDF the running FP64 sum of
+    |alpha|^2 in index order and norm its last entry. A u whose product with
+    the norm is not below every CDF value (only by rounding) gets the last j
+    of non-zero probability."""
+    p = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    cdf = np.cumsum(p)
+    idx = np.searchsorted(cdf, np.asarray(u, dtype=np.float64) * cdf[-1], side="right")
+    nz = np.flatnonzero(p)
+    last = int(nz[-1]) if len(nz) else 0
+    return np.where(idx >= len(p), last, idx).astype(np.uint64)
+
+
 def uniform_amplitude(n: int) -> float:
     """Every amplitude of H on each qubit of |0...0>: 2^(-n/2)."""
     return 2.0 ** (-n / 2)

@@ -73,6 +73,12 @@ def uniform53(u64: np.ndarray) -> np.ndarray:
     return (u64 >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
+def sorted_uniforms(seed: int, count: int) -> np.ndarray:
+    """`count` uniforms in [0, 1) (SplitMix64, 53 bits), sorted ascending: the
+    draws of a measurement sample."""
+    return np.sort(uniform53(splitmix64(seed, count)))
+
+
 def normals(seed: int, count: int) -> np.ndarray:
     """`count` standard normals by Box-Muller with u1 <- 1 - u1 (so u1 > 0)."""
     pairs = (count + 1) // 2

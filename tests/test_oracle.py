@@ -275,3 +275,35 @@ def test_mcu_stride_tier_matches_dense_tier(controls, t):
     got2 = psi.copy()
     oracle.run_circuit(got2, qc.gate_mcu(controls, t, u))
     assert np.array_equal(got2, got)
+
+
+def test_sampling_of_a_basis_state_and_of_the_uniform_state():
+    """Measurement (section Quantum Circuits) of |x> always gives x; of the
+    uniform state (H on every qubit, even n: every probability exactly 2^-n,
+    so every CDF value is exact) the draw u gives floor(u 2^n) exactly."""
+    u = qc.sorted_uniforms(5, 4000)
+    for n, x in ((1, 1), (6, 37), (10, 1000)):
+        assert (oracle.sample_indices(oracle.basis_state(n, x), u) == x).all()
+    for n in (2, 8, 12):
+        psi = np.full(1 << n, oracle.uniform_amplitude(n), dtype=np.complex128)
+        want = np.floor(u * 2.0 ** n).astype(np.uint64)
+        assert np.array_equal(oracle.sample_indices(psi, u), want), n
+
+
+def test_sampling_frequencies_follow_the_probabilities():
+    """Chi-square of 200k draws from a seeded 8-qubit state against |alpha|^2:
+    a dropped square or a shifted index fails it."""
+    n = 8
+    psi = qc.random_state(n, 808)
+    p = np.abs(psi) ** 2
+    u = qc.sorted_uniforms(9, 200000)
+    counts = np.bincount(oracle.sample_indices(psi, u).astype(np.int64), minlength=1 << n)
+    exp = p * len(u)
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    # 255 degrees of freedom: mean 255, sd ~22.6; a wrong distribution gives thousands
+    assert chi2 < 400, chi2
+    # zero-probability indices are never drawn, and draws near 1 take the last non-zero index
+    psi2 = np.zeros(16, dtype=np.complex128)
+    psi2[[2, 5, 9]] = [0.6, 0.0, 0.8]
+    got = oracle.sample_indices(psi2, np.array([0.0, 0.35, 0.37, 0.999999, np.nextafter(1.0, 0.0)]))
+    assert list(got) == [2, 2, 9, 9, 9]
