@@ -123,6 +123,11 @@ sv_status sv_info(sv_state s, void **dev_ptr, int *n_qubits, sv_dtype *dtype);
 /* Sets the state to the basis state |basis_index> (basis_index < 2^n). */
 sv_status sv_reset(sv_state s, uint64_t basis_index);
 
+/* Sets the state to the uniform superposition 2^{-n/2} sum_x |x>: H on every
+ * qubit of |0...0> (section Quantum Information Processing), written in one
+ * pass instead of n gate passes. */
+sv_status sv_reset_uniform(sv_state s);
+
 /* Applies the 2x2 matrix m to qubit `target`: the stride update of section
  * State Vector Partitioning, one pass over the state. */
 sv_status sv_apply_1q(sv_state s, int target, const double m[8]);
@@ -174,6 +179,20 @@ sv_status sv_copy_in(sv_state s, const void *host_src);
 
 /* Waits for the handle's stream; SV_EDEVICE if queued work failed. */
 sv_status sv_synchronize(sv_state s);
+
+/* Measurement sampling: draws basis indices with probability |alpha_j|^2 /
+ * norm (the measurement of section Quantum Circuits) by inverting the CDF,
+ * CDF(j) = sum_{k <= j} |alpha_k|^2 in FP64 (summed in blocks of 4096
+ * amplitudes): out_dev[i] = the j with CDF(j - 1) <= u_dev[i] * norm <
+ * CDF(j). u_dev: `count` doubles in device memory, in [0, 1) and ascending
+ * (the caller's uniform draws, sorted); other input leaves out_dev
+ * unspecified. A u whose product with the norm rounds to the norm or above
+ * gets the last index of non-zero probability; a state of norm 0 gives 0.
+ * out_dev: `count` uint64 in device memory. Queued on the handle's stream;
+ * the first call allocates scratch of about 2^(n-11) doubles (SV_ENOMEM if
+ * that fails). Reads the state once, plus once more for the blocks of 4096
+ * amplitudes that receive samples. */
+sv_status sv_sample_device(sv_state s, const double *u_dev, uint64_t count, uint64_t *out_dev);
 
 /* ---- planned circuits and batched launches --------------------------------
  * A plan is a circuit fused into tile passes (as SV_FUSE does) and uploaded to

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
-    "sv_info", "sv_reset", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_cphase",
+    "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
@@ -74,6 +74,8 @@ _SIGNATURES = {
     "sv_apply_1q": ([_vp, _int, _dp], _int),
     "sv_apply_ctrl": ([_vp, _int, _int, _dp], _int),
     "sv_apply_mcu": ([_vp, ctypes.c_uint64, _int, _dp], _int),
+    "sv_reset_uniform": ([_vp], _int),
+    "sv_sample_device": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
     "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
     "sv_probs": ([_vp, _u64, _u64, _dp], _int),
@@ -173,6 +175,16 @@ def sv_info(h: int):
 
 def sv_reset(h: int, basis_index: int = 0) -> None:
     _check(lib().sv_reset(h, basis_index))
+
+
+def sv_reset_uniform(h: int) -> None:
+    _check(lib().sv_reset_uniform(h))
+
+
+def sv_sample_device(h: int, u_dev: int, count: int, out_dev: int) -> None:
+    """Device pointers: `count` ascending doubles in [0, 1) in, `count` uint64
+    indices out (see include/sv.h)."""
+    _check(lib().sv_sample_device(h, u_dev, count, out_dev))
 
 
 def sv_apply_1q(h: int, target: int, m) -> None:
@@ -381,6 +393,21 @@ class StateVector:
         if count is None:
             count = (1 << self.n) - first
         return sv_probs(self.handle, first, count)
+
+    def reset_uniform(self):
+        sv_reset_uniform(self.handle)
+
+    def sample(self, u) -> np.ndarray:
+        """Basis indices drawn by the uniforms `u` (ascending, in [0, 1))."""
+        import torch
+        with torch.cuda.stream(self.stream):   # copies ordered with the handle's work
+            ud = torch.as_tensor(np.ascontiguousarray(u, dtype=np.float64)).to(self.tensor.device)
+            out = torch.empty(len(ud), dtype=torch.int64, device=self.tensor.device)
+            if len(ud):
+                sv_sample_device(self.handle, ud.data_ptr(), len(ud), out.data_ptr())
+            host = out.cpu()
+        self.synchronize()
+        return host.numpy().view(np.uint64)
 
     def norm(self) -> float:
         return sv_norm(self.handle)

@@ -11,7 +11,8 @@ namespace svk {
 const char *class_name(int cls)
 {
     static const char *names[KC_COUNT] = {"init", "pair", "pair_ctrl", "swap", "diag",
-                                          "tile", "dense", "norm", "probs", "batch"};
+                                          "tile", "dense", "norm", "probs", "batch",
+                                          "sample"};
     return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
 

@@ -272,6 +272,7 @@ sv_status sv_destroy(sv_state s)
     svk::plan_release(s);
     svk::prof_release(s);
     if (s->scratch) (void)hipFree(s->scratch);
+    if (s->sample_scratch) (void)hipFree(s->sample_scratch);
     if (s->owned && s->psi) (void)hipFree(s->psi);
     delete s;
     if (e != hipSuccess) return hip_fail(e, "stream synchronize in sv_destroy");
@@ -304,6 +305,19 @@ sv_status sv_reset(sv_state s, uint64_t basis_index)
     hipError_t e = svk::launch_init(s->psi, s->n, s->dt, basis_index, s->stream);
     svk::prof_end(s, tok, svk::KC_INIT, double(state_bytes(s)), 0);
     if (e != hipSuccess) return hip_fail(e, "init kernel launch");
+    return SV_OK;
+}
+
+sv_status sv_reset_uniform(sv_state s)
+{
+    if (sv_status st = check_handle(s)) return st;
+    DeviceScope ds(s->device);
+    // 2^{-n/2}: exact for even n, one rounding of 1/sqrt(2) otherwise
+    const double amp = std::ldexp(s->n % 2 ? std::sqrt(0.5) : 1.0, -(s->n / 2));
+    const int tok = svk::prof_begin(s);
+    hipError_t e = svk::launch_fill(s->psi, s->n, s->dt, amp, s->stream);
+    svk::prof_end(s, tok, svk::KC_INIT, double(state_bytes(s)), 0);
+    if (e != hipSuccess) return hip_fail(e, "uniform init kernel launch");
     return SV_OK;
 }
 
@@ -541,6 +555,39 @@ sv_status sv_synchronize(sv_state s)
     if (sv_status st = check_handle(s)) return st;
     DeviceScope ds(s->device);
     SV_HIP(hipStreamSynchronize(s->stream), "stream synchronize");
+    return SV_OK;
+}
+
+sv_status sv_sample_device(sv_state s, const double *u_dev, uint64_t count, uint64_t *out_dev)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (count == 0) return SV_OK;
+    if (!u_dev || !out_dev) return fail(SV_EINVAL, "null device pointer");
+    DeviceScope ds(s->device);
+    const uint64_t need = svk::sample_scratch_doubles(s->n);
+    if (s->sample_cap < need) {
+        if (s->sample_scratch) {
+            SV_HIP(hipStreamSynchronize(s->stream), "stream synchronize");
+            (void)hipFree(s->sample_scratch);
+            s->sample_scratch = nullptr;
+            s->sample_cap = 0;
+        }
+        hipError_t e = hipMalloc(&s->sample_scratch, need * sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SV_ENOMEM, "hipMalloc of sampling scratch failed: %s", hipGetErrorString(e));
+        }
+        s->sample_cap = need;
+    }
+    const double N = std::ldexp(1.0, s->n), sb = svk::elem_bytes(s->dt);
+    const int tok = svk::prof_begin(s);
+    hipError_t e = svk::launch_block_sums(s->psi, s->n, s->dt, s->sample_scratch, s->stream);
+    if (e == hipSuccess)
+        e = svk::launch_sample(s->psi, s->n, s->dt, s->sample_scratch, u_dev, count, out_dev,
+                               s->stream);
+    // algorithmic bytes: the state once, the draws and the indices
+    svk::prof_end(s, tok, svk::KC_SAMPLE, N * sb + double(count) * 16.0, 3.0 * N);
+    if (e != hipSuccess) return hip_fail(e, "sampling kernel launch");
     return SV_OK;
 }
 

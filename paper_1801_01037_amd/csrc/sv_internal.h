@@ -62,7 +62,7 @@ bool is_phase_diag(const double m[8]);    // diag(1, e^{i phi}) with |e^{i phi}|
 // Kernel classes reported by sv_profile_read, in this order.
 enum KernelClass {
     KC_INIT = 0, KC_PAIR, KC_PAIR_CTRL, KC_SWAP, KC_DIAG, KC_TILE, KC_DENSE, KC_NORM,
-    KC_PROBS, KC_BATCH, KC_COUNT
+    KC_PROBS, KC_BATCH, KC_SAMPLE, KC_COUNT
 };
 const char *class_name(int cls);
 
@@ -81,6 +81,26 @@ struct Profiler {
 
 }  // namespace svk
 
+namespace svk {
+// ---- measurement sampling and the uniform state (kernels_sample.hip) ------
+constexpr int kSampleBlockLog = 12;                 // amplitudes per block: 4096
+constexpr int kSampleBlock = 1 << kSampleBlockLog;
+// Doubles of scratch sampling needs: the block sums, their exclusive prefix
+// with the norm at its end, and the index of the last non-zero block.
+inline uint64_t sample_scratch_doubles(int n)
+{
+    const uint64_t nb = n < kSampleBlockLog ? 1 : (uint64_t(1) << (n - kSampleBlockLog));
+    return 2 * nb + 2;
+}
+// S: sample_scratch_doubles(n) doubles of device scratch.
+hipError_t launch_block_sums(const void *psi, int n, sv_dtype dt, double *S, hipStream_t st);
+// u: m ascending doubles in [0, 1) (device); out: m indices (device).
+hipError_t launch_sample(const void *psi, int n, sv_dtype dt, const double *S, const double *u,
+                         uint64_t m, uint64_t *out, hipStream_t st);
+// Every amplitude set to (value, 0).
+hipError_t launch_fill(void *psi, int n, sv_dtype dt, double value, hipStream_t st);
+}  // namespace svk
+
 struct sv_state_s {
     void *psi = nullptr;
     int n = 0;
@@ -89,6 +109,8 @@ struct sv_state_s {
     bool owned = false;
     int device = 0;
     double *scratch = nullptr;        // kNormBlocks + 1 doubles (norm partials + result)
+    double *sample_scratch = nullptr; // sampling scratch, allocated on first use
+    uint64_t sample_cap = 0;          // its size in doubles
     svk::Profiler prof;
     void *plan = nullptr;             // planner buffers (plan.hip)
 };
