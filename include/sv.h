@@ -81,13 +81,21 @@ typedef struct {
  * (one pass over the state per gate). */
 #define SV_FUSE        1u  /* group gates into LDS-tile passes: each pass reads and */
                            /* writes the state once and applies every gate whose    */
-                           /* target lies in the pass's tile qubits                 */
+                           /* target lies in the pass's tile qubits. Between passes */
+                           /* the qubits are relabelled (the paper's non-sequential */
+                           /* storage of the state vector, section Non-Sequential   */
+                           /* Storage): a pass writes its tile back with the next   */
+                           /* gates' qubits in the low index bits every tile must   */
+                           /* hold. The state is in the standard order again when   */
+                           /* the call's work completes                             */
 #define SV_FUSE_DENSE  2u  /* group gates into dense 2^k x 2^k blocks on k <= 5      */
                            /* qubits, multiplied on the matrix cores (MFMA)          */
-#define SV_GRAPH       4u  /* capture the launches of this call in a HIP graph and   */
-                           /* replay it; the graph is cached on the handle keyed by  */
-                           /* the gate list, so a repeated identical call only       */
-                           /* replays                                                */
+#define SV_GRAPH       4u  /* sv_batch_run only (see there): capture the level      */
+                           /* launches in a HIP graph and replay it. sv_run_circuit */
+                           /* rejects it with SV_EUNSUPPORTED                        */
+#define SV_NO_RELABEL  8u  /* with SV_FUSE: keep the standard storage order between */
+                           /* passes (qubits 0..2, or 0..3 for complex64, in every  */
+                           /* tile)                                                  */
 
 /* ABI version; bumped when a signature or struct changes. */
 int sv_version(void);
@@ -149,8 +157,8 @@ sv_status sv_apply_mcu(sv_state s, uint64_t control_mask, int target, const doub
 sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
 
 /* Applies n_gates gates in order (the circuit of section Quantum Circuits).
- * The gate array is read during the call only. flags: 0, SV_FUSE,
- * SV_FUSE_DENSE, optionally | SV_GRAPH. Fusion reorders only gates that act on
+ * The gate array is read during the call only. flags: 0, SV_FUSE (optionally
+ * | SV_NO_RELABEL) or SV_FUSE_DENSE. Fusion reorders only gates that act on
  * disjoint qubits, so the result equals the in-order product up to rounding.
  * All gates are validated before any work is queued. */
 sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags);
@@ -244,7 +252,8 @@ sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t co
  * groups, *n_ops ops in execution order; gate_op[i] (n_gates entries, or
  * NULL) receives the index of the last op that applies gate i. Gates are
  * validated as in sv_run_circuit for an n_qubits register. flags must be
- * SV_FUSE. Any out pointer may be NULL. */
+ * SV_FUSE, optionally | SV_NO_RELABEL (passes that restore the standard
+ * order count as passes). Any out pointer may be NULL. */
 sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
                           uint32_t flags, int32_t *gate_op, int32_t *n_passes, int32_t *n_groups,
                           int32_t *n_ops);

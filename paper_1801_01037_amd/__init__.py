@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SVError", "lib",
+    "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
     "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
@@ -34,6 +34,7 @@ SV_C128 = 2
 SV_FUSE = 1
 SV_FUSE_DENSE = 2
 SV_GRAPH = 4
+SV_NO_RELABEL = 8
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
 _STATUS_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM",

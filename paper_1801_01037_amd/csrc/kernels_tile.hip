@@ -7,7 +7,9 @@
 // thread pulls the 2^K amplitudes that differ in the group's register bits S
 // into registers, applies every op of the group there (pair updates on a
 // target in S; controls anywhere; diagonal phases), and puts them back. The
-// tile is then written to its original place. LDS slots are padded by one
+// tile is then written to its original place, optionally with its qubits in
+// another order (the planner's relabelling of storage bits inside the tile,
+// which leaves the amplitudes the tile covers unchanged). LDS slots are padded by one
 // element every 256 bytes so that register gathers with large local strides
 // spread over the banks.
 #include <type_traits>
@@ -322,6 +324,34 @@ __device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &o
     }
 }
 
+// Write-back of a group with exit exchanges: register combination r goes to
+// the slot of combination x(r) (the affine map of TileGroup), which is one of
+// this thread's own slots.
+template <bool C64, int K>
+__device__ __forceinline__ void write_exit(AmpT<C64> *lds, const Amps<C64, K> &val, uint32_t lbase,
+                                           const uint32_t (&soff)[K], CGroup &G)
+{
+    constexpr int NR = 1 << K;
+    uint32_t mb = lbase, ms[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        mb |= ((G.xb >> k) & 1u) ? soff[k] : 0u;
+        uint32_t m = 0;
+        const uint32_t col = G.xs[k];
+#pragma unroll
+        for (int k2 = 0; k2 < K; ++k2) m |= ((col >> k2) & 1u) ? soff[k2] : 0u;
+        ms[k] = m;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        uint32_t l = mb;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) l ^= ms[k];
+        lds[lds_slot<C64>(l)] = val[r];
+    }
+}
+
 // Work-group barrier that orders LDS accesses only: global loads issued
 // before it may still be in flight after it.
 __device__ __forceinline__ void lds_barrier()
@@ -356,6 +386,19 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
     uint64_t roff[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) roff[r] = deposit(uint64_t(r) * W, a.tmask);
+    // Relabelled store: output local index lo reads input local index
+    // perm(lo), bit j of lo moving to bit osrc_j; perm(tid + r W) =
+    // perm(tid) | perm(r W).
+    const bool permute = a.permute != 0;
+    const uint64_t osrc = a.osrc;
+    uint32_t proff[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        uint32_t x = 0;
+        for (int k = 0; k < K; ++k)
+            x |= uint32_t((r >> k) & 1) << uint32_t((osrc >> (4 * (a.L - K + k))) & 15u);
+        proff[r] = x;
+    }
 
     for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
@@ -395,17 +438,26 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                     v[r] = lds[lds_slot<C64>(l)];
                 }
                 // Ops alternate v -> w and w -> v; the group ends in either.
+                // The write-back applies the group's exit exchanges: only this
+                // thread's own slots are permuted, so no barrier is needed.
                 const int nops = G.nops;
+                const bool exit_map = G.has_exit != 0;
                 for (int oi = 0;; oi += 2) {
                     if (oi == nops) {
+                        if (exit_map) write_exit<C64, K>(lds, v, lbase, soff, G);
+                        else {
 #pragma unroll
-                        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+                            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = v[r];
+                        }
                         break;
                     }
                     apply_op<C64, K>(v, w, li, ops[G.op0 + oi], dtab, a.L, G, g, gbase, tid, tab);
                     if (oi + 1 == nops) {
+                        if (exit_map) write_exit<C64, K>(lds, w, lbase, soff, G);
+                        else {
 #pragma unroll
-                        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = w[r];
+                            for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(li[r])] = w[r];
+                        }
                         break;
                     }
                     apply_op<C64, K>(w, v, li, ops[G.op0 + oi + 1], dtab, a.L, G, g, gbase, tid, tab);
@@ -413,15 +465,25 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
             }
             lds_barrier();
         }
-        // Each thread stores the slots it filled, so the next fill needs no barrier.
+        // Each thread stores the slots it filled, so the next fill needs no
+        // barrier, unless the store is relabelled and reads other slots.
         if (active) {
             uint64_t dts = dt;
             uint32_t ts = tid;
             asm volatile("" : "+v"(dts), "+v"(ts));
             const uint64_t gb = gbase | dts;
+            if (permute) {
+                uint32_t pt = 0;
+                for (int j = 0; j < a.L - K; ++j)
+                    pt |= ((ts >> j) & 1u) << uint32_t((osrc >> (4 * j)) & 15u);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(ts + uint32_t(r) * W)];
+                for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(pt | proff[r])];
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(ts + uint32_t(r) * W)];
+            }
         }
+        if (permute) lds_barrier();
     }
 }
 
@@ -464,7 +526,7 @@ __global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
         a.psi = pc.psi; a.groups = pc.groups; a.ops = pc.ops; a.dtab = pc.dtab;
         a.phase_tab = pc.phase_tab; a.tmask = pc.tmask; a.omask = pc.omask; a.ntiles = pc.ntiles;
         a.L = pc.L; a.nlow = pc.nlow; a.nnon = pc.nnon; a.group0 = pc.group0;
-        a.ngroups = pc.ngroups; a.has_diag = pc.has_diag;
+        a.ngroups = pc.ngroups; a.has_diag = pc.has_diag; a.permute = pc.permute; a.osrc = pc.osrc;
         if (threadIdx.x == 0) b.t_start[ti] = wall_clock64();
         const uint32_t size = 1u << a.L;
         A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));

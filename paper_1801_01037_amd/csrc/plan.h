@@ -24,7 +24,8 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
 
 int plan_dense_inspect(int n, const sv_gate *gates, size_t n_gates, uint64_t *masks,
                        double *mats, int cap);
-int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32_t *gate_op,
+int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool relabel,
+                 int32_t *gate_op,
                  int32_t *n_passes, int32_t *n_groups, int32_t *n_ops);
 
 }  // namespace svk

@@ -14,7 +14,13 @@
 //     with everything on other qubits, so held-back phases merge into few
 //     diagonal ops. Phases are kept as exact uint64 fractions of a turn;
 //   * inside a pass, consecutive ops whose targets fit in K register bits form
-//     a group (one LDS exchange per group).
+//     a group (one LDS exchange per group); runs of gates on two qubits are
+//     multiplied into 4x4 ops, and exchanges that end a group ride on its
+//     write-back. Two ways of forming the blocks are tried per pass and the
+//     one with the lower estimated cost is kept;
+//   * between passes the qubits may be relabelled (section Non-Sequential
+//     Storage of the State Vector): a pass writes its tile back with the
+//     qubits the next gates need in the index bits every tile must hold.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -113,7 +119,28 @@ void apply_to_4x4(const POp &op, int q0, double *mat /* 4x4 complex, row major *
 // move ahead of ops it shares no qubit with. Ops with a control outside the
 // register qubits, and diagonal ops, are kept as they are. A run of a single op
 // is kept too (an exchange or a 2x2 is cheaper than a 4x4).
-std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq)
+// Estimated cost of one op in a tile pass, in FP64 operations per amplitude:
+// its arithmetic plus a fixed part (reading the op record, one pass of the
+// register amplitudes from one array to the other). Fitted to measured
+// passes: a 4x4 costs about 3.3 times an exchange and 1.6 times a 2x2.
+double op_cost(const POp &op)
+{
+    switch (op.kind) {
+    case TOP_U4: return 43.0;
+    case TOP_U: return 27.0;
+    case TOP_SWAP: return 13.0;
+    default: return 25.0;   // TOP_DIAG
+    }
+}
+constexpr double kGroupCost = 25.0;   // one LDS exchange of the register amplitudes
+constexpr double kPassFloor = 415.0;  // a pass's HBM time on the same scale
+
+// spread = false: each block is seeded with the first two-qubit op left;
+// spread = true: a two-qubit op that reaches the front of the list stays
+// alone, and a block is seeded with the first two-qubit op on the front op's
+// qubit. On layered circuits the second lets one 4x4 take two layers of
+// one-qubit gates around every other layer of CNOTs, which stay exchanges.
+std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq, bool spread)
 {
     auto absorbable = [&](const POp &op) {
         if (op.kind != TOP_U && op.kind != TOP_SWAP) return false;
@@ -121,16 +148,22 @@ std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq)
     };
     std::vector<POp> out;
     while (!ops.empty()) {
-        if (!absorbable(ops.front())) {
+        // A two-qubit op with no op left before it stays alone: the one-qubit
+        // ops that follow it can join the next block on their qubits for free,
+        // and a block seeded here would cost a 4x4 for what an exchange or a
+        // controlled 2x2 does.
+        if (!absorbable(ops.front()) ||
+            (spread && __builtin_popcountll(op_qmask(ops.front())) == 2)) {
             out.push_back(std::move(ops.front()));
             ops.erase(ops.begin());
             continue;
         }
-        // Seed the block with the qubits of the first two-qubit op that can
-        // join, so that it collects the one-qubit ops around that gate.
+        // Seed the block with the qubits of a two-qubit op, so that it
+        // collects the one-qubit ops before and after that gate.
         uint64_t seed = op_qmask(ops.front());
         for (const POp &op : ops)
-            if (absorbable(op) && __builtin_popcountll(op_qmask(op)) == 2) {
+            if (absorbable(op) && __builtin_popcountll(op_qmask(op)) == 2 &&
+                (!spread || (op_qmask(op) & seed))) {
                 seed = op_qmask(op);
                 break;
             }
@@ -151,9 +184,16 @@ std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq)
             }
         }
         uint64_t P = 0;
-        for (const POp &m : members) P |= op_qmask(m);
-        if (members.size() == 1) {
-            out.push_back(std::move(members.front()));
+        double alone = 0;   // cost of the members as they are
+        for (const POp &m : members) {
+            P |= op_qmask(m);
+            alone += op_cost(m);
+        }
+        POp probe;
+        probe.kind = TOP_U4;
+        if (members.size() == 1 || (__builtin_popcountll(P) == 2 && alone <= op_cost(probe))) {
+            // a 4x4 would not be cheaper
+            for (POp &m : members) out.push_back(std::move(m));
         } else if (__builtin_popcountll(P) == 1) {
             // product of 2x2s on one qubit (each later op multiplies on the left)
             POp f;
@@ -206,12 +246,119 @@ std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq)
 struct PGroup {
     std::vector<int> S;   // local positions
     std::vector<POp> ops;
+    std::vector<POp> folded;   // exchanges applied by the write-back (TileGroup exit map)
+    uint32_t xb = 0;
+    uint32_t xs[kTileMaxK] = {1, 2, 4, 8};
 };
 
+// Moves the exchanges (X, CNOT) on register qubits that no later op of the
+// group touches out of the op list into the group's exit map: they commute
+// with every later op, so they can be applied last, as a permutation of each
+// thread's register combinations when the group writes back to LDS.
+void fold_exit(PGroup &g, const std::vector<int> &T)
+{
+    uint64_t regq = 0;   // storage bits of the register positions
+    for (int sidx : g.S) regq |= uint64_t(1) << T[sidx];
+    auto rpos = [&](int b) {
+        for (int k = 0; k < int(g.S.size()); ++k)
+            if (T[g.S[k]] == b) return k;
+        return -1;
+    };
+    uint64_t kept = 0;
+    std::vector<char> out(g.ops.size(), 0);
+    bool any = false;
+    for (int i = int(g.ops.size()) - 1; i >= 0; --i) {
+        const POp &op = g.ops[i];
+        const uint64_t qm = op_qmask(op);
+        const bool exch = op.kind == TOP_SWAP && ((regq >> op.target) & 1) &&
+                          (op.control < 0 || ((regq >> op.control) & 1));
+        if (exch && !(qm & kept)) {
+            out[i] = 1;
+            any = true;
+        } else {
+            kept |= qm;
+        }
+    }
+    if (!any) return;
+    std::vector<POp> keep, fold;
+    for (size_t i = 0; i < g.ops.size(); ++i) (out[i] ? fold : keep).push_back(std::move(g.ops[i]));
+    // x = E_m ... E_1 (r): an X on position t adds e_t, a CNOT c -> t adds
+    // bit c to bit t; composed in gate order on the columns and the constant.
+    for (const POp &op : fold) {
+        const int t = rpos(op.target);
+        if (op.control < 0) {
+            g.xb ^= 1u << t;
+            continue;
+        }
+        const int c = rpos(op.control);
+        for (int k = 0; k < kTileMaxK; ++k) g.xs[k] ^= ((g.xs[k] >> c) & 1u) << t;
+        g.xb ^= ((g.xb >> c) & 1u) << t;
+    }
+    g.ops = std::move(keep);
+    g.folded = std::move(fold);
+}
+
 struct PPass {
-    std::vector<int> T;   // global bits, ascending
+    std::vector<int> T;   // index bits of the tile (storage positions), ascending
     std::vector<PGroup> groups;
+    std::vector<int> osrc;   // output local bit j takes input local bit osrc[j]
+                             // (empty: the tile is written back in its own order)
 };
+
+// Storage order of the qubits between passes (the paper's non-sequential
+// storage of the state vector): logical qubit q is stored at index bit
+// pos[q]; inv is the inverse. A pass may permute the qubits of its own tile
+// on the way out, so its tile still covers the same amplitudes and it stays
+// in place.
+struct Layout {
+    std::vector<int> pos, inv;
+    explicit Layout(int n) : pos(n), inv(n)
+    {
+        for (int q = 0; q < n; ++q) pos[q] = inv[q] = q;
+    }
+    bool identity() const
+    {
+        for (size_t q = 0; q < pos.size(); ++q)
+            if (pos[q] != int(q)) return false;
+        return true;
+    }
+};
+
+// Rewrites an op's qubits as storage positions.
+void to_storage(POp &op, const std::vector<int> &pos)
+{
+    if (op.target >= 0) op.target = pos[op.target];
+    if (op.control >= 0) op.control = pos[op.control];
+    for (PPivot &P : op.piv) {
+        P.p = pos[P.p];
+        for (DTerm &t : P.terms)
+            if (t.wbit >= 0) t.wbit = pos[t.wbit];
+    }
+}
+
+// Qubits in the order a restoring pass wants them: each cycle of the storage
+// permutation walked from a qubit held in the low index bits (q, then the
+// qubit whose home q occupies, ...), then the other cycles. A tile holding a
+// run of a cycle sends every member but the first home.
+std::vector<int> cycle_order(const Layout &lay, int nlow)
+{
+    const int n = int(lay.pos.size());
+    std::vector<char> seen(n, 0);
+    std::vector<int> out;
+    auto walk = [&](int start) {
+        int q = start;
+        while (!seen[q]) {
+            seen[q] = 1;
+            out.push_back(q);
+            q = lay.pos[q];
+        }
+    };
+    for (int b = 0; b < nlow && b < n; ++b)
+        if (lay.inv[b] != b) walk(lay.inv[b]);
+    for (int q = 0; q < n; ++q)
+        if (lay.pos[q] != q) walk(q);
+    return out;
+}
 
 struct TileGeom {
     int L, K, nlow;
@@ -301,16 +448,107 @@ void flush_diag(std::map<int, PPivot> &pending, uint64_t qm, std::vector<POp> &o
     }
 }
 
+// Register groups of one pass, by the light-cone rule: a group gets up to K
+// register qubits (a target, both qubits of a 4x4, and a control when it is a
+// tile qubit and fits), and takes every op whose register qubits it holds and
+// that touches no qubit of an op left for a later group. Diagonal ops need no
+// register qubit. Ops only move ahead of ops on other qubits. `ops` are in
+// storage bits; T is the tile's storage bits (ascending) and Pm their mask.
+// With `spread`, two-qubit blocks are formed over the whole pass first (so a
+// block is not cut where one group's light cone ends) with the spread rule of
+// fuse_group.
+std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::vector<int> &T,
+                                const TileGeom &geo, bool spread)
+{
+    auto local = [&](int b) { return int(std::lower_bound(T.begin(), T.end(), b) - T.begin()); };
+    if (spread) ops = fuse_group(std::move(ops), Pm, true);
+    std::vector<PGroup> groups;
+    while (!ops.empty()) {
+        PGroup cur;
+        uint64_t Sq = 0, blocked = 0;
+        std::vector<POp> later;
+        for (POp &op : ops) {
+            const uint64_t qm = op_qmask(op);
+            if (qm & blocked) {
+                blocked |= qm;
+                later.push_back(std::move(op));
+                continue;
+            }
+            if (op.kind == TOP_DIAG) {
+                cur.ops.push_back(std::move(op));
+                continue;
+            }
+            const uint64_t need = op.kind == TOP_U4 ? qm : uint64_t(1) << op.target;
+            uint64_t want = need;
+            if (op.kind != TOP_U4 && op.control >= 0 && ((Pm >> op.control) & 1))
+                want |= uint64_t(1) << op.control;
+            if (__builtin_popcountll(Sq | want) <= geo.K) {
+                Sq |= want;
+            } else if (__builtin_popcountll(Sq | need) <= geo.K) {
+                Sq |= need;
+            } else {
+                blocked |= qm;
+                later.push_back(std::move(op));
+                continue;
+            }
+            cur.ops.push_back(std::move(op));
+        }
+        for (int b = 0; b < 64; ++b)
+            if ((Sq >> b) & 1) cur.S.push_back(local(b));
+        groups.push_back(std::move(cur));
+        ops.swap(later);
+    }
+    for (PGroup &g : groups) {
+        // Pad S with the highest unused local bits so the threads of a
+        // wave differ in low local bits (contiguous LDS slots).
+        for (int b = geo.L - 1; b >= 0 && int(g.S.size()) < geo.K; --b)
+            if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) g.S.push_back(b);
+        std::sort(g.S.begin(), g.S.end());
+        if (geo.fuse4 && geo.K >= 2) {
+            uint64_t regq = 0;
+            for (int sidx : g.S) regq |= uint64_t(1) << T[sidx];
+            g.ops = fuse_group(std::move(g.ops), regq, spread);
+        }
+        if (geo.K == kTileMaxK) fold_exit(g, T);
+    }
+    return groups;
+}
+
+double groups_cost(const std::vector<PGroup> &groups)
+{
+    double c = kGroupCost * double(groups.size());
+    for (const PGroup &g : groups)
+        for (const POp &op : g.ops) c += op_cost(op);
+    return c;
+}
+
 // Splits the items into passes. *ok is false if some item could not be
 // placed (the geometry left no free tile bit); the plan is then incomplete.
-std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Item> &items, bool *ok)
+//
+// With `relabel`, each pass also chooses the storage order it leaves behind:
+// the index bits 0..nlow-1, which every tile must hold (whole 128-byte
+// lines), receive tile qubits that the next gates need, instead of always
+// holding qubits 0..nlow-1. The last pass (or, when it cannot, extra passes
+// without gates) returns the state to the standard order.
+std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector<Item> &items,
+                                   bool *ok, bool relabel)
 {
     *ok = true;
     std::vector<PPass> passes;
     std::vector<Item> rem = items;
-    while (!rem.empty()) {
-        uint64_t Tm = (geo.nlow >= 64) ? ~uint64_t(0) : ((uint64_t(1) << geo.nlow) - 1);
-        int tcount = geo.nlow;
+    Layout lay(n);
+    int restores = 0;
+    while (!rem.empty() || !lay.identity()) {
+        if (rem.empty() && ++restores > 2 * n + 2) {   // cannot happen: each restore fixes a qubit
+            *ok = false;
+            break;
+        }
+        uint64_t Tm = 0;   // logical qubits of the tile
+        int tcount = 0;
+        for (int b = 0; b < geo.nlow; ++b) {
+            Tm |= uint64_t(1) << lay.inv[b];
+            ++tcount;
+        }
         uint64_t blocked = 0;
         std::vector<Item> next;
         std::vector<POp> ops;
@@ -359,80 +597,140 @@ std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Ite
             ops.push_back(std::move(op));
         }
         flush_diag(pending, ~uint64_t(0), ops);
-        if (ops.empty()) {   // no progress: refuse rather than drop gates
+        if (ops.empty() && !rem.empty()) {   // no progress: refuse rather than drop gates
             *ok = false;
             break;
         }
-        // Fill T up to L bits with the lowest unused qubits.
-        for (int b = 0; b < n && tcount < geo.L; ++b)
-            if (!((Tm >> b) & 1)) {
-                Tm |= uint64_t(1) << b;
+        auto take = [&](int q) {
+            if (tcount < geo.L && !((Tm >> q) & 1)) {
+                Tm |= uint64_t(1) << q;
                 ++tcount;
             }
-        PPass pass;
-        for (int b = 0; b < n; ++b)
-            if ((Tm >> b) & 1) pass.T.push_back(b);
-        auto local = [&](int q) {
-            return int(std::lower_bound(pass.T.begin(), pass.T.end(), q) - pass.T.begin());
         };
-        // Groups, by the light-cone rule: a group gets up to K register
-        // qubits (a target, and its control when it is a tile qubit and
-        // fits), and takes every op whose target is a register qubit and that
-        // touches no qubit of an op left for a later group. Diagonal ops need
-        // no register qubit. Ops only move ahead of ops on other qubits.
-        {
-            std::vector<POp> rem_ops = std::move(ops);
-            while (!rem_ops.empty()) {
-                PGroup cur;
-                uint64_t Sq = 0, blocked = 0;
-                std::vector<POp> later;
-                for (POp &op : rem_ops) {
-                    const uint64_t qm = op_qmask(op);
-                    if (qm & blocked) {
-                        blocked |= qm;
-                        later.push_back(std::move(op));
-                        continue;
-                    }
-                    if (op.kind == TOP_DIAG) {
-                        cur.ops.push_back(std::move(op));
-                        continue;
-                    }
-                    const uint64_t need = uint64_t(1) << op.target;
-                    uint64_t want = need;
-                    if (op.control >= 0 && ((Tm >> op.control) & 1)) want |= uint64_t(1) << op.control;
-                    if (__builtin_popcountll(Sq | want) <= geo.K) {
-                        Sq |= want;
-                    } else if (__builtin_popcountll(Sq | need) <= geo.K) {
-                        Sq |= need;
-                    } else {
-                        blocked |= qm;
-                        later.push_back(std::move(op));
-                        continue;
-                    }
-                    cur.ops.push_back(std::move(op));
+        const bool last = next.empty();
+        if (relabel) {
+            if (last) {
+                // Room left goes to the qubits out of their home bits.
+                for (int q : cycle_order(lay, geo.nlow)) take(q);
+            } else {
+                // Room left goes to the qubits the next gates touch, so that
+                // they can be left in the low index bits.
+                for (const Item &it : next) {
+                    if (tcount >= geo.L) break;
+                    for (uint64_t m = it.qmask; m; m &= m - 1) take(__builtin_ctzll(m));
                 }
-                for (int b = 0; b < 64; ++b)
-                    if ((Sq >> b) & 1) cur.S.push_back(local(b));
-                pass.groups.push_back(std::move(cur));
-                rem_ops.swap(later);
             }
         }
-        for (PGroup &g : pass.groups) {
-            // Pad S with the highest unused local bits so the threads of a
-            // wave differ in low local bits (contiguous LDS slots).
-            for (int b = geo.L - 1; b >= 0 && int(g.S.size()) < geo.K; --b)
-                if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) g.S.push_back(b);
-            std::sort(g.S.begin(), g.S.end());
-            if (geo.fuse4 && geo.K >= 2) {
-                uint64_t regq = 0;
-                for (int sidx : g.S) regq |= uint64_t(1) << pass.T[sidx];
-                g.ops = fuse_group(std::move(g.ops), regq);
+        // Fill T up to L qubits with the lowest unused ones.
+        for (int b = 0; b < n && tcount < geo.L; ++b) take(b);
+        PPass pass;
+        uint64_t Pm = 0;   // the tile's index bits in storage
+        for (int q = 0; q < n; ++q)
+            if ((Tm >> q) & 1) Pm |= uint64_t(1) << lay.pos[q];
+        for (int b = 0; b < n; ++b)
+            if ((Pm >> b) & 1) pass.T.push_back(b);
+        for (POp &op : ops) to_storage(op, lay.pos);
+        auto local = [&](int b) {
+            return int(std::lower_bound(pass.T.begin(), pass.T.end(), b) - pass.T.begin());
+        };
+        if (relabel) {
+            // The storage order this pass leaves: first the qubits wanted in
+            // the low bits (the next gates' qubits among the tile's, in gate
+            // order; none after the last pass), then every other tile qubit at
+            // its home bit if the tile holds that bit, else where it was, else
+            // anywhere free in the tile.
+            std::vector<int> want;
+            if (!last) {
+                for (const Item &it : next) {
+                    for (uint64_t m = it.qmask & Tm; m && int(want.size()) < geo.nlow; m &= m - 1) {
+                        const int q = __builtin_ctzll(m);
+                        if (std::find(want.begin(), want.end(), q) == want.end()) want.push_back(q);
+                    }
+                    if (int(want.size()) >= geo.nlow) break;
+                }
+                for (int b = 0; b < geo.nlow && int(want.size()) < geo.nlow; ++b)
+                    if (std::find(want.begin(), want.end(), lay.inv[b]) == want.end())
+                        want.push_back(lay.inv[b]);
             }
+            std::vector<int> np(n, -1);
+            std::vector<char> used(n, 0);
+            auto place = [&](int q, int b) {
+                np[q] = b;
+                used[b] = 1;
+            };
+            for (int q : want)
+                if (q < geo.nlow) place(q, q);
+            for (int q : want)
+                if (np[q] < 0 && lay.pos[q] < geo.nlow && !used[lay.pos[q]]) place(q, lay.pos[q]);
+            for (int q : want)
+                if (np[q] < 0)
+                    for (int b = 0; b < geo.nlow; ++b)
+                        if (!used[b]) {
+                            place(q, b);
+                            break;
+                        }
+            for (int q = 0; q < n; ++q)
+                if (((Tm >> q) & 1) && np[q] < 0 && ((Pm >> q) & 1) && !used[q] &&
+                    (q >= geo.nlow || want.empty()))
+                    place(q, q);
+            for (int q = 0; q < n; ++q)
+                if (((Tm >> q) & 1) && np[q] < 0 && !used[lay.pos[q]] &&
+                    (lay.pos[q] >= geo.nlow || want.empty()))
+                    place(q, lay.pos[q]);
+            for (int q = 0; q < n; ++q)
+                if (((Tm >> q) & 1) && np[q] < 0)
+                    for (int b : pass.T)
+                        if (!used[b]) {
+                            place(q, b);
+                            break;
+                        }
+            pass.osrc.assign(geo.L, 0);
+            bool moved = false;
+            for (int q = 0; q < n; ++q)
+                if ((Tm >> q) & 1) {
+                    pass.osrc[local(np[q])] = local(lay.pos[q]);
+                    moved |= np[q] != lay.pos[q];
+                }
+            for (int q = 0; q < n; ++q)
+                if ((Tm >> q) & 1) {
+                    lay.pos[q] = np[q];
+                    lay.inv[np[q]] = q;
+                }
+            if (!moved) pass.osrc.clear();
+        }
+        // Groups, made both ways; the cheaper set is kept.
+        {
+            std::vector<PGroup> ga = make_groups(ops, Pm, pass.T, geo, false);
+            if (geo.fuse4 && geo.K >= 2) {
+                std::vector<PGroup> gb = make_groups(std::move(ops), Pm, pass.T, geo, true);
+                if (groups_cost(gb) < groups_cost(ga)) ga.swap(gb);
+            }
+            pass.groups = std::move(ga);
         }
         passes.push_back(std::move(pass));
         rem.swap(next);
     }
     return passes;
+}
+
+// With `relabel`, both plans are made and the one with the lower estimated
+// cost is kept (each pass costs the larger of its HBM time and its ops; a
+// short circuit can lose more to the passes that restore the standard order
+// than it gains).
+std::vector<PPass> plan_passes(int n, const TileGeom &geo, const std::vector<Item> &items, bool *ok,
+                               bool relabel = false)
+{
+    std::vector<PPass> fixed = plan_passes_one(n, geo, items, ok, false);
+    if (!relabel || !*ok) return fixed;
+    bool ok_r = true;
+    std::vector<PPass> moved = plan_passes_one(n, geo, items, &ok_r, true);
+    auto cost = [](const std::vector<PPass> &ps) {
+        double c = 0;
+        for (const PPass &p : ps) c += std::max(kPassFloor, groups_cost(p.groups));
+        return c;
+    };
+    if (ok_r && cost(moved) < cost(fixed)) return moved;
+    return fixed;
 }
 
 // ---- flattening and execution ---------------------------------------------
@@ -554,6 +852,9 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
         a.group0 = int(f.groups.size());
         a.ngroups = int(pass.groups.size());
         a.has_diag = 0;
+        a.permute = pass.osrc.empty() ? 0 : 1;
+        a.osrc = 0;
+        for (int j = 0; j < int(pass.osrc.size()); ++j) a.osrc |= uint64_t(pass.osrc[j]) << (4 * j);
         double flops = 0;
         auto local = [&](int q) {
             return int(std::lower_bound(pass.T.begin(), pass.T.end(), q) - pass.T.begin());
@@ -567,6 +868,9 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                 if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) tg.ns[nn++] = b;
             tg.op0 = int(f.ops.size());
             tg.nops = int(g.ops.size());
+            tg.has_exit = g.folded.empty() ? 0 : 1;
+            tg.xb = g.xb;
+            for (int k = 0; k < kTileMaxK; ++k) tg.xs[k] = g.xs[k];
             for (const POp &op : g.ops) {
                 TileOp to{};
                 to.kind = op.kind;
@@ -778,14 +1082,15 @@ static sv_status stage_upload(sv_state s, size_t bytes, const std::function<void
     return SV_OK;
 }
 
-static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, std::string *err)
+static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
+                           std::string *err)
 {
     const TileGeom geo = geometry(s->n, s->dt);
     std::vector<Item> items;
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
     bool ok = true;
-    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok, relabel);
     if (!ok) {
         *err = "planner could not place every gate with this tile geometry";
         return SV_EUNSUPPORTED;
@@ -863,13 +1168,13 @@ sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t fl
                    std::string *err)
 {
     if (flags & SV_GRAPH) {
-        *err = "SV_GRAPH is not built yet";
+        *err = "SV_GRAPH applies to sv_batch_run only";
         return SV_EUNSUPPORTED;
     }
     // Dense blocks need at least 16 columns of 32 amplitudes (n >= 9); smaller
     // registers are fused into tiles instead.
     if ((flags & SV_FUSE_DENSE) && s->n >= 9) return run_dense(s, gates, n_gates, err);
-    return run_tiles(s, gates, n_gates, err);
+    return run_tiles(s, gates, n_gates, !(flags & SV_NO_RELABEL), err);
 }
 
 void plan_release(sv_state s)
@@ -906,14 +1211,14 @@ int plan_dense_inspect(int n, const sv_gate *gates, size_t n_gates, uint64_t *ma
 }
 
 // Host-only view of a plan, for inspection and tests.
-int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32_t *gate_op,
-                 int32_t *n_passes, int32_t *n_groups, int32_t *n_ops)
+int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool relabel,
+                 int32_t *gate_op, int32_t *n_passes, int32_t *n_groups, int32_t *n_ops)
 {
     const TileGeom geo = geometry(n, dt);
     std::vector<Item> items;
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
     bool ok = true;
-    const std::vector<PPass> passes = plan_passes(n, geo, items, &ok);
+    const std::vector<PPass> passes = plan_passes(n, geo, items, &ok, relabel);
     if (!ok) return -1;
     int32_t seq = 0, groups = 0;
     if (gate_op)
@@ -921,11 +1226,12 @@ int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, int32
     for (const PPass &p : passes) {
         for (const PGroup &g : p.groups) {
             ++groups;
-            for (const POp &op : g.ops) {
-                if (gate_op)
-                    for (int gi : op.gates) gate_op[gi] = std::max(gate_op[gi], seq);
-                ++seq;
-            }
+            for (const std::vector<POp> *list : {&g.ops, &g.folded})
+                for (const POp &op : *list) {
+                    if (gate_op)
+                        for (int gi : op.gates) gate_op[gi] = std::max(gate_op[gi], seq);
+                    ++seq;
+                }
         }
     }
     if (n_passes) *n_passes = int32_t(passes.size());

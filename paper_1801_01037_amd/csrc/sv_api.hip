@@ -369,7 +369,10 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
     if (sv_status st = check_handle(s)) return st;
     if (n_gates == 0) return SV_OK;
     if (!gates) return fail(SV_EINVAL, "null gate array");
-    if (flags & ~(SV_FUSE | SV_FUSE_DENSE | SV_GRAPH)) return fail(SV_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(SV_FUSE | SV_FUSE_DENSE | SV_GRAPH | SV_NO_RELABEL))
+        return fail(SV_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & SV_NO_RELABEL) && !(flags & SV_FUSE))
+        return fail(SV_EINVAL, "SV_NO_RELABEL applies to SV_FUSE only");
     if ((flags & SV_FUSE) && (flags & SV_FUSE_DENSE))
         return fail(SV_EINVAL, "SV_FUSE and SV_FUSE_DENSE are exclusive");
     for (size_t i = 0; i < n_gates; ++i)
@@ -505,14 +508,16 @@ sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, si
     if (!valid_dtype(dtype)) return fail(SV_EINVAL, "unknown dtype %d", int(dtype));
     if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [1, 34]", n_qubits);
     if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
-    if (flags != SV_FUSE) return fail(SV_EUNSUPPORTED, "only SV_FUSE plans can be inspected");
+    if ((flags & ~SV_NO_RELABEL) != SV_FUSE)
+        return fail(SV_EUNSUPPORTED, "only SV_FUSE plans can be inspected");
     sv_state_s probe;
     probe.n = n_qubits;
     probe.dt = dtype;
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
     if (sv_status st = reject_mcu(gates, n_gates)) return st;
-    if (svk::plan_inspect(n_qubits, dtype, gates, n_gates, gate_op, n_passes, n_groups, n_ops) != 0)
+    if (svk::plan_inspect(n_qubits, dtype, gates, n_gates, !(flags & SV_NO_RELABEL), gate_op, n_passes,
+                          n_groups, n_ops) != 0)
         return fail(SV_EUNSUPPORTED, "planner could not place every gate with this tile geometry");
     return SV_OK;
 }

@@ -67,6 +67,13 @@ struct TileGroup {
     int32_t s[kTileMaxK];          // local tile bits held in registers, ascending
     int32_t ns[kTileMaxL];         // the other L-K local bits, ascending
     int32_t op0, nops;
+    // Exchanges (X, CNOT) on register bits that end the group are not ops:
+    // the write-back sends register combination r to position
+    // x(r) = xb ^ (xor of xs[k] over the set bits k of r), an affine map on
+    // the K register positions (has_exit = 0: x(r) = r).
+    int32_t has_exit;
+    uint32_t xb;
+    uint32_t xs[kTileMaxK];
 };
 
 struct TileArgs {
@@ -83,6 +90,9 @@ struct TileArgs {
     int32_t nnon;                  // index bits outside the tile
     int32_t group0, ngroups;
     int32_t has_diag;              // the pass holds diagonal ops (load phase_tab)
+    int32_t permute;               // the tile is written back in another qubit order:
+    uint64_t osrc;                 // output local bit j takes input local bit
+                                   // (osrc >> 4 j) & 15
 };
 
 // Dynamic LDS of one work-group: padded tile plus the phase table.

@@ -13,9 +13,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _alone(r):
+    """The request run alone with the plan the server uses (plans keep the
+    standard storage order)."""
     h = sv.sv_create(r.n, r.dtype)
     try:
-        sv.sv_run_circuit(h, r.gates, sv.SV_FUSE)
+        sv.sv_run_circuit(h, r.gates, sv.SV_FUSE | sv.SV_NO_RELABEL)
         return sv.sv_copy_out(h)
     finally:
         sv.sv_destroy(h)

@@ -133,3 +133,49 @@ def test_plans_reject_gates_with_several_controls():
         with pytest.raises(sv.SVError) as e:
             sv.sv_plan_inspect(6, sv.SV_C128, bad)
         assert e.value.status == sv.SV_EINVAL
+
+
+# ---- relabelling between passes (non-sequential storage) ---------------------
+
+@pytest.mark.parametrize("dtype", [sv.SV_C128, sv.SV_C64], ids=["c128", "c64"])
+def test_relabelling_cuts_passes_of_layered_circuits(dtype):
+    """Every tile must hold the index bits of one 128-byte line; relabelling
+    puts the next gates' qubits there instead of qubits 0..2 (0..3 for
+    complex64), so a layered circuit needs far fewer passes."""
+    g = qc.layer_circuit(30, 20, 1)
+    fixed = sv.sv_plan_inspect(30, dtype, g, sv.SV_FUSE | sv.SV_NO_RELABEL)[1]
+    moved = sv.sv_plan_inspect(30, dtype, g, sv.SV_FUSE)[1]
+    assert fixed >= 25 and moved <= 18, (fixed, moved)
+    g = qc.layer_circuit(18, 40, 1840)
+    fixed = sv.sv_plan_inspect(18, dtype, g, sv.SV_FUSE | sv.SV_NO_RELABEL)[1]
+    moved = sv.sv_plan_inspect(18, dtype, g, sv.SV_FUSE)[1]
+    assert moved * 2 < fixed, (fixed, moved)
+
+
+def test_relabelling_never_adds_passes_and_keeps_order():
+    """Passes that restore the standard order are counted; the planner keeps
+    the fixed-order plan when relabelling would not save a pass. Gate order
+    per qubit holds in either plan."""
+    rng = np.random.default_rng(77)
+    for trial in range(60):
+        n = int(rng.integers(1, 35))
+        kind = trial % 3
+        if kind == 0:
+            g = qc.layer_circuit(n, int(rng.integers(1, 40)), trial)
+        elif kind == 1:
+            g = qc.qft_circuit(n)
+        else:
+            g = np.concatenate([qc.qft_circuit(n), qc.layer_circuit(n, 5, trial)])
+        for dtype in (sv.SV_C128, sv.SV_C64):
+            fixed = sv.sv_plan_inspect(n, dtype, g, sv.SV_FUSE | sv.SV_NO_RELABEL)[1]
+            moved = sv.sv_plan_inspect(n, dtype, g, sv.SV_FUSE)[1]
+            assert moved <= fixed, (n, kind, fixed, moved)
+            if n <= 20 and trial % 6 == 0:
+                check_plan_order(n, dtype, g)
+
+
+def test_no_relabel_needs_fuse():
+    g = qc.layer_circuit(5, 2, 1)
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_inspect(5, sv.SV_C128, g, sv.SV_FUSE_DENSE | sv.SV_NO_RELABEL)
+    assert e.value.status == sv.SV_EUNSUPPORTED
