@@ -216,7 +216,11 @@ typedef struct sv_plan_s *sv_plan;
 typedef struct sv_batch_s *sv_batch;
 
 /* Plans gates for state s (n >= 4) and uploads the plan (synchronous). The
- * gate array is read during the call only. */
+ * gate array is read during the call only. The plan is the one SV_FUSE makes
+ * (same passes, same results bit for bit), relabelling included: between two
+ * of its passes the state may be stored in another qubit order, and it is in
+ * the standard order again after the plan's last pass. Read or change the
+ * state only before the first or after the last pass has run. */
 sv_status sv_plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out);
 /* Frees the plan's device memory (waits for work that may use it). */
 sv_status sv_plan_destroy(sv_plan p);

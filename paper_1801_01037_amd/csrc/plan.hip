@@ -146,61 +146,76 @@ std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq, bool spread)
         if (op.kind != TOP_U && op.kind != TOP_SWAP) return false;
         return op.control < 0 || ((regq >> op.control) & 1);
     };
+    std::vector<uint64_t> qmask(ops.size());
+    uint64_t all_q = 0;   // every qubit the ops touch
+    for (size_t i = 0; i < ops.size(); ++i) all_q |= qmask[i] = op_qmask(ops[i]);
+    auto is2q = [&](int i) { return __builtin_popcountll(qmask[i]) == 2; };
     std::vector<POp> out;
-    while (!ops.empty()) {
-        // A two-qubit op with no op left before it stays alone: the one-qubit
-        // ops that follow it can join the next block on their qubits for free,
-        // and a block seeded here would cost a 4x4 for what an exchange or a
-        // controlled 2x2 does.
-        if (!absorbable(ops.front()) ||
-            (spread && __builtin_popcountll(op_qmask(ops.front())) == 2)) {
-            out.push_back(std::move(ops.front()));
-            ops.erase(ops.begin());
+    out.reserve(ops.size());
+    std::vector<int> live(ops.size()), members, next;
+    for (size_t i = 0; i < ops.size(); ++i) live[i] = int(i);
+    size_t head = 0;   // live[head..] are the ops still to place, in order
+    while (head < live.size()) {
+        const int f = live[head];
+        // With `spread`, a two-qubit op with no op left before it stays alone:
+        // the one-qubit ops that follow it can join the next block on their
+        // qubits, and a block seeded here would cost a 4x4 for what an
+        // exchange or a controlled 2x2 does.
+        if (!absorbable(ops[f]) || (spread && is2q(f))) {
+            out.push_back(std::move(ops[f]));
+            ++head;
             continue;
         }
         // Seed the block with the qubits of a two-qubit op, so that it
         // collects the one-qubit ops before and after that gate.
-        uint64_t seed = op_qmask(ops.front());
-        for (const POp &op : ops)
-            if (absorbable(op) && __builtin_popcountll(op_qmask(op)) == 2 &&
-                (!spread || (op_qmask(op) & seed))) {
-                seed = op_qmask(op);
+        uint64_t seed = qmask[f];
+        for (size_t k = head; k < live.size(); ++k) {
+            const int i = live[k];
+            if (absorbable(ops[i]) && is2q(i) && (!spread || (qmask[i] & seed))) {
+                seed = qmask[i];
                 break;
             }
-        std::vector<POp> members, next;
+        }
+        members.clear();
         for (int attempt = 0; attempt < 2 && members.empty(); ++attempt) {
-            if (attempt == 1) seed = op_qmask(ops.front());   // the seed could not join
+            if (attempt == 1) seed = qmask[f];   // the seed could not join
             uint64_t P = seed, blocked = 0;
             next.clear();
-            for (POp &op : ops) {
-                const uint64_t qm = op_qmask(op);
-                if ((qm & blocked) || !absorbable(op) || __builtin_popcountll(P | qm) > 2) {
+            for (size_t k = head; k < live.size(); ++k) {
+                const int i = live[k];
+                const uint64_t qm = qmask[i];
+                if ((blocked & all_q) == all_q) {   // nothing later can join
+                    next.insert(next.end(), live.begin() + long(k), live.end());
+                    break;
+                }
+                if ((qm & blocked) || !absorbable(ops[i]) || __builtin_popcountll(P | qm) > 2) {
                     blocked |= qm;
-                    next.push_back(op);
+                    next.push_back(i);
                     continue;
                 }
                 P |= qm;
-                members.push_back(op);
+                members.push_back(i);
             }
         }
         uint64_t P = 0;
         double alone = 0;   // cost of the members as they are
-        for (const POp &m : members) {
-            P |= op_qmask(m);
-            alone += op_cost(m);
+        for (int i : members) {
+            P |= qmask[i];
+            alone += op_cost(ops[i]);
         }
         POp probe;
         probe.kind = TOP_U4;
         if (members.size() == 1 || (__builtin_popcountll(P) == 2 && alone <= op_cost(probe))) {
             // a 4x4 would not be cheaper
-            for (POp &m : members) out.push_back(std::move(m));
+            for (int i : members) out.push_back(std::move(ops[i]));
         } else if (__builtin_popcountll(P) == 1) {
             // product of 2x2s on one qubit (each later op multiplies on the left)
-            POp f;
-            f.kind = TOP_U;
-            f.target = members.front().target;
+            POp fo;
+            fo.kind = TOP_U;
+            fo.target = ops[members.front()].target;
             double acc[8] = {1, 0, 0, 0, 0, 0, 1, 0};
-            for (const POp &mop : members) {
+            for (int i : members) {
+                const POp &mop = ops[i];
                 double g[8];
                 if (mop.kind == TOP_SWAP) {
                     const double x[8] = {0, 0, 1, 0, 1, 0, 0, 0};
@@ -209,36 +224,37 @@ std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq, bool spread)
                     std::memcpy(g, mop.m, sizeof g);
                 }
                 double r[8];
-                for (int i = 0; i < 2; ++i)
-                    for (int j = 0; j < 2; ++j) {
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
                         double re = 0, im = 0;
                         for (int k = 0; k < 2; ++k) {
-                            const double gr = g[(2 * i + k) * 2], gi = g[(2 * i + k) * 2 + 1];
-                            const double ar = acc[(2 * k + j) * 2], ai = acc[(2 * k + j) * 2 + 1];
+                            const double gr = g[(2 * a + k) * 2], gi = g[(2 * a + k) * 2 + 1];
+                            const double ar = acc[(2 * k + b) * 2], ai = acc[(2 * k + b) * 2 + 1];
                             re += gr * ar - gi * ai;
                             im += gr * ai + gi * ar;
                         }
-                        r[(2 * i + j) * 2] = re;
-                        r[(2 * i + j) * 2 + 1] = im;
+                        r[(2 * a + b) * 2] = re;
+                        r[(2 * a + b) * 2 + 1] = im;
                     }
                 std::memcpy(acc, r, sizeof acc);
-                f.gates.insert(f.gates.end(), mop.gates.begin(), mop.gates.end());
+                fo.gates.insert(fo.gates.end(), mop.gates.begin(), mop.gates.end());
             }
-            std::memcpy(f.m, acc, sizeof acc);
-            out.push_back(std::move(f));
+            std::memcpy(fo.m, acc, sizeof acc);
+            out.push_back(std::move(fo));
         } else {
-            POp f;
-            f.kind = TOP_U4;
-            f.q0 = __builtin_ctzll(P);
-            f.q1 = 63 - __builtin_clzll(P);
-            for (int i = 0; i < 4; ++i) f.m4[(i * 4 + i) * 2] = 1.0;
-            for (const POp &mop : members) {
-                apply_to_4x4(mop, f.q0, f.m4);
-                f.gates.insert(f.gates.end(), mop.gates.begin(), mop.gates.end());
+            POp fo;
+            fo.kind = TOP_U4;
+            fo.q0 = __builtin_ctzll(P);
+            fo.q1 = 63 - __builtin_clzll(P);
+            for (int k = 0; k < 4; ++k) fo.m4[(k * 4 + k) * 2] = 1.0;
+            for (int i : members) {
+                apply_to_4x4(ops[i], fo.q0, fo.m4);
+                fo.gates.insert(fo.gates.end(), ops[i].gates.begin(), ops[i].gates.end());
             }
-            out.push_back(std::move(f));
+            out.push_back(std::move(fo));
         }
-        ops.swap(next);
+        live.swap(next);
+        head = 0;
     }
     return out;
 }
@@ -462,16 +478,28 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
 {
     auto local = [&](int b) { return int(std::lower_bound(T.begin(), T.end(), b) - T.begin()); };
     if (spread) ops = fuse_group(std::move(ops), Pm, true);
+    std::vector<uint64_t> qmask(ops.size());
+    std::vector<int> rest(ops.size()), later;
+    for (size_t i = 0; i < ops.size(); ++i) {
+        qmask[i] = op_qmask(ops[i]);
+        rest[i] = int(i);
+    }
     std::vector<PGroup> groups;
-    while (!ops.empty()) {
+    while (!rest.empty()) {
         PGroup cur;
         uint64_t Sq = 0, blocked = 0;
-        std::vector<POp> later;
-        for (POp &op : ops) {
-            const uint64_t qm = op_qmask(op);
+        later.clear();
+        for (size_t k = 0; k < rest.size(); ++k) {
+            const int i = rest[k];
+            POp &op = ops[i];
+            const uint64_t qm = qmask[i];
+            if ((blocked & Pm) == Pm) {   // nothing later can join
+                later.insert(later.end(), rest.begin() + long(k), rest.end());
+                break;
+            }
             if (qm & blocked) {
                 blocked |= qm;
-                later.push_back(std::move(op));
+                later.push_back(i);
                 continue;
             }
             if (op.kind == TOP_DIAG) {
@@ -488,7 +516,7 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
                 Sq |= need;
             } else {
                 blocked |= qm;
-                later.push_back(std::move(op));
+                later.push_back(i);
                 continue;
             }
             cur.ops.push_back(std::move(op));
@@ -496,7 +524,7 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
         for (int b = 0; b < 64; ++b)
             if ((Sq >> b) & 1) cur.S.push_back(local(b));
         groups.push_back(std::move(cur));
-        ops.swap(later);
+        rest.swap(later);
     }
     for (PGroup &g : groups) {
         // Pad S with the highest unused local bits so the threads of a
@@ -535,7 +563,9 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
 {
     *ok = true;
     std::vector<PPass> passes;
-    std::vector<Item> rem = items;
+    // Items still to place, as indices into `items`, in gate order.
+    std::vector<int> rem(items.size());
+    for (size_t k = 0; k < items.size(); ++k) rem[k] = int(k);
     Layout lay(n);
     int restores = 0;
     while (!rem.empty() || !lay.identity()) {
@@ -550,12 +580,18 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
             ++tcount;
         }
         uint64_t blocked = 0;
-        std::vector<Item> next;
+        std::vector<int> next;
         std::vector<POp> ops;
         std::map<int, PPivot> pending;
-        for (const Item &it : rem) {
+        const uint64_t all = n >= 64 ? ~uint64_t(0) : (uint64_t(1) << n) - 1;
+        for (size_t ii = 0; ii < rem.size(); ++ii) {
+            const Item &it = items[rem[ii]];
+            if (blocked == all) {   // nothing later can join this pass
+                next.insert(next.end(), rem.begin() + long(ii), rem.end());
+                break;
+            }
             if (it.qmask & blocked) {
-                next.push_back(it);
+                next.push_back(rem[ii]);
                 blocked |= it.qmask;
                 continue;
             }
@@ -567,7 +603,7 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
                         Tm |= uint64_t(1) << it.pivot;
                         ++tcount;
                     } else {
-                        next.push_back(it);
+                        next.push_back(rem[ii]);
                         blocked |= it.qmask;
                         continue;
                     }
@@ -582,7 +618,7 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
                     Tm |= uint64_t(1) << it.target;
                     ++tcount;
                 } else {
-                    next.push_back(it);
+                    next.push_back(rem[ii]);
                     blocked |= it.qmask;
                     continue;
                 }
@@ -615,7 +651,8 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
             } else {
                 // Room left goes to the qubits the next gates touch, so that
                 // they can be left in the low index bits.
-                for (const Item &it : next) {
+                for (int idx : next) {
+                    const Item &it = items[idx];
                     if (tcount >= geo.L) break;
                     for (uint64_t m = it.qmask; m; m &= m - 1) take(__builtin_ctzll(m));
                 }
@@ -641,7 +678,8 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
             // anywhere free in the tile.
             std::vector<int> want;
             if (!last) {
-                for (const Item &it : next) {
+                for (int idx : next) {
+                    const Item &it = items[idx];
                     for (uint64_t m = it.qmask & Tm; m && int(want.size()) < geo.nlow; m &= m - 1) {
                         const int q = __builtin_ctzll(m);
                         if (std::find(want.begin(), want.end(), q) == want.end()) want.push_back(q);
@@ -1320,7 +1358,7 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
     bool ok = true;
-    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok);
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok, true);
     if (!ok) {
         *err = "planner could not place every gate with this tile geometry";
         return SV_EUNSUPPORTED;

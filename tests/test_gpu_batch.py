@@ -16,11 +16,11 @@ def _specs(count, seed, n_lo=10, n_hi=18, d_lo=4, d_hi=30):
 
 
 def _run_alone(n, dtype, g):
-    """The circuit run alone with the plan a batch uses (plans keep the
-    standard storage order), so results are bitwise equal."""
+    """The circuit run alone with SV_FUSE, which makes the plan a batch uses,
+    so results are bitwise equal."""
     h = sv.sv_create(n, dtype)
     try:
-        sv.sv_run_circuit(h, g, sv.SV_FUSE | sv.SV_NO_RELABEL)
+        sv.sv_run_circuit(h, g, sv.SV_FUSE)
         return sv.sv_copy_out(h)
     finally:
         sv.sv_destroy(h)

@@ -13,11 +13,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _alone(r):
-    """The request run alone with the plan the server uses (plans keep the
-    standard storage order)."""
+    """The request run alone with SV_FUSE, which makes the plan the server
+    uses."""
     h = sv.sv_create(r.n, r.dtype)
     try:
-        sv.sv_run_circuit(h, r.gates, sv.SV_FUSE | sv.SV_NO_RELABEL)
+        sv.sv_run_circuit(h, r.gates, sv.SV_FUSE)
         return sv.sv_copy_out(h)
     finally:
         sv.sv_destroy(h)
