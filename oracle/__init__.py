@@ -37,6 +37,9 @@ def load(path: str):
     L.orc_apply_cphase.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_double]
     L.orc_apply_mcu.argtypes = [dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, dp]
+    L.orc_apply_unitary.argtypes = [dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.c_int, dp]
+    L.orc_apply_unitary.restype = ctypes.c_int
     L.orc_run_circuit.argtypes = [dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t]
     L.orc_run_circuit.restype = ctypes.c_int
     L.orc_probs.argtypes = [dp, ctypes.c_uint64, ctypes.c_uint64, dp]
@@ -95,6 +98,22 @@ def apply_mcu(psi: np.ndarray, controls, t: int, m) -> None:
         mask |= 1 << int(c)
     m = np.ascontiguousarray(m, dtype=np.float64)
     lib().orc_apply_mcu(_dp(psi.view(np.float64)), n, mask, t, _dp(m))
+
+
+def apply_unitary(psi: np.ndarray, qubits, u) -> None:
+    """General gate: the 2^k x 2^k complex matrix u on qubits (q_0, ...,
+    q_{k-1}), q_0 the least significant bit of the local index."""
+    n = _check_state(psi)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    k = len(q)
+    u = np.ascontiguousarray(u, dtype=np.complex128)
+    if u.shape != (1 << k, 1 << k):
+        raise ValueError("u must be 2^k x 2^k")
+    rc = lib().orc_apply_unitary(_dp(psi.view(np.float64)), n,
+                                 q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), k,
+                                 _dp(u.view(np.float64)))
+    if rc != 0:
+        raise ValueError("bad qubits for apply_unitary")
 
 
 def apply_cphase(psi: np.ndarray, c: int, t: int, theta: float) -> None:

@@ -54,6 +54,25 @@ def operator_mcu(n: int, controls, t: int, q: np.ndarray) -> np.ndarray:
     return np.eye(2 ** n, dtype=np.complex128) + _kron_chain(factors, n)
 
 
+def operator_unitary(n: int, qubits, u: np.ndarray) -> np.ndarray:
+    """The general gate u on (q_0, ..., q_{k-1}) as a sum of Kronecker chains:
+    u = sum_{r,c} u[r, c] |r><c|, and |r><c| on k qubits is the product of the
+    2x2 matrix units |r_m><c_m| on qubit q_m (r_m = bit m of r)."""
+    k = len(qubits)
+    out = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
+    for r in range(2 ** k):
+        for c in range(2 ** k):
+            if u[r, c] == 0:
+                continue
+            factors = {}
+            for m, q in enumerate(qubits):
+                e = np.zeros((2, 2), dtype=np.complex128)
+                e[(r >> m) & 1, (c >> m) & 1] = 1.0
+                factors[int(q)] = e
+            out += u[r, c] * _kron_chain(factors, n)
+    return out
+
+
 def operator_cphase(n: int, c: int, t: int, theta: float) -> np.ndarray:
     return operator_ctrl(n, c, t, np.diag([1.0, np.exp(1j * theta)]))
 

@@ -22,7 +22,13 @@
  *   - controlled-phase is the controlled gate with Q = diag(1, e^{i theta});
  *   - a gate with several controls (the Toffoli, or controlled-controlled-NOT,
  *     gate of section Quantum Circuits is X with two) updates only where every
- *     control bit is set.
+ *     control bit is set;
+ *   - a general gate U on k qubits (q_0, ..., q_{k-1}) is the 2^k x 2^k
+ *     operator of the tensor-product rule of section Quantum Information
+ *     Processing acting on those qubits' factor: for every setting of the
+ *     other index bits, the 2^k amplitudes a_c, c = sum_m b_{q_m} 2^m, become
+ *     sum_c U[r][c] a_c (q_0 is the least significant bit of c, so U = B (x) A
+ *     applies A to q_0 and B to q_1).
  *
  * Arithmetic: every complex product is written out in real arithmetic and the
  * file is built with -ffp-contract=off, so each operation rounds once.
@@ -106,6 +112,67 @@ void orc_apply_mcu(double *psi, int n, uint64_t cmask, int t, const double m[8])
         for (uint64_t k = j; k < j + stride; ++k)
             if ((k & cmask) == cmask)
                 pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
+}
+
+/* General gate on k <= 6 distinct qubits q[0..k-1] (see the header): U is
+ * 2^k x 2^k complex, row major, (re, im) interleaved. The outer loop runs over
+ * the 2^(n-k) settings of the other bits (g with zeros inserted at the qubit
+ * positions, in increasing order); each product is written out in real
+ * arithmetic and the terms are summed in column order. Returns 0, or -1 for
+ * bad arguments. */
+int orc_apply_unitary(double *psi, int n, const int *q, int k, const double *U)
+{
+    if (k < 1 || k > 6 || k > n)
+        return -1;
+    int sorted[6];
+    for (int m = 0; m < k; ++m) {
+        if (q[m] < 0 || q[m] >= n)
+            return -1;
+        for (int m2 = 0; m2 < m; ++m2)
+            if (q[m2] == q[m])
+                return -1;
+        sorted[m] = q[m];
+    }
+    for (int a = 1; a < k; ++a)        /* insertion sort of the positions */
+        for (int b = a; b > 0 && sorted[b - 1] > sorted[b]; --b) {
+            int t = sorted[b]; sorted[b] = sorted[b - 1]; sorted[b - 1] = t;
+        }
+    const uint64_t D = (uint64_t)1 << k;
+    const uint64_t G = (uint64_t)1 << (n - k);
+    uint64_t off[64];                  /* index offset of local combination c */
+    for (uint64_t c = 0; c < D; ++c) {
+        off[c] = 0;
+        for (int m = 0; m < k; ++m)
+            if ((c >> m) & 1u)
+                off[c] |= (uint64_t)1 << q[m];
+    }
+    double a[128], out[128];
+    for (uint64_t g = 0; g < G; ++g) {
+        uint64_t base = g;             /* insert a zero at each qubit position */
+        for (int m = 0; m < k; ++m) {
+            uint64_t low = base & (((uint64_t)1 << sorted[m]) - 1);
+            base = ((base >> sorted[m]) << (sorted[m] + 1)) | low;
+        }
+        for (uint64_t c = 0; c < D; ++c) {
+            a[2 * c] = psi[2 * (base | off[c])];
+            a[2 * c + 1] = psi[2 * (base | off[c]) + 1];
+        }
+        for (uint64_t r = 0; r < D; ++r) {
+            double re = 0.0, im = 0.0;
+            for (uint64_t c = 0; c < D; ++c) {
+                double ur = U[2 * (r * D + c)], ui = U[2 * (r * D + c) + 1];
+                re += ur * a[2 * c] - ui * a[2 * c + 1];
+                im += ur * a[2 * c + 1] + ui * a[2 * c];
+            }
+            out[2 * r] = re;
+            out[2 * r + 1] = im;
+        }
+        for (uint64_t r = 0; r < D; ++r) {
+            psi[2 * (base | off[r])] = out[2 * r];
+            psi[2 * (base | off[r]) + 1] = out[2 * r + 1];
+        }
+    }
+    return 0;
 }
 
 /* Controlled phase: the controlled gate with Q = diag(1, e^{i theta}). */

@@ -110,6 +110,17 @@ def haar_su2(seed: int, count: int) -> np.ndarray:
     return np.stack([a, b, c, d, -c, d, a, -b], axis=1)
 
 
+def random_unitary(k: int, seed: int) -> np.ndarray:
+    """A seeded Haar-random 2^k x 2^k unitary (complex128): the Q factor of a
+    complex Gaussian matrix, with the phases of R's diagonal moved into Q."""
+    d = 1 << k
+    g = normals(seed, 2 * d * d)
+    z = (g[0::2] + 1j * g[1::2]).reshape(d, d)
+    q, r = np.linalg.qr(z)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return q * ph[np.newaxis, :]
+
+
 def gate_u(target: int, m) -> np.ndarray:
     g = np.zeros(1, GATE_DTYPE)
     g["kind"], g["control"], g["target"] = G_U, -1, target

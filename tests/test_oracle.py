@@ -277,6 +277,85 @@ def test_mcu_stride_tier_matches_dense_tier(controls, t):
     assert np.array_equal(got2, got)
 
 
+# ---- general gates on k qubits -----------------------------------------------
+
+def test_unitary_on_one_qubit_is_the_stride_update():
+    """k = 1 is the paper's pair update itself, bit for bit."""
+    n = 7
+    m = qc.haar_su2(5, 1)[0]
+    u = dense.matrix_of(m)
+    for t in (0, 3, 6):
+        psi = qc.random_state(n, 40 + t)
+        a, b = psi.copy(), psi.copy()
+        oracle.apply_1q(a, t, m)
+        oracle.apply_unitary(b, (t,), u)
+        assert np.array_equal(a, b)
+
+
+def test_unitary_tensor_product_of_one_qubit_gates():
+    """U = B (x) A on (q0, q1) is A on q0 and B on q1 (tensor-product rule;
+    q0 is the low bit of the local index), for both qubit orders."""
+    n = 6
+    ma, mb = qc.haar_su2(9, 2)
+    A, B = dense.matrix_of(ma), dense.matrix_of(mb)
+    for q0, q1 in ((1, 4), (4, 1), (0, 5), (3, 2)):
+        psi = qc.random_state(n, 7 * q0 + q1)
+        ref = psi.copy()
+        oracle.apply_1q(ref, q0, ma)
+        oracle.apply_1q(ref, q1, mb)
+        got = psi.copy()
+        oracle.apply_unitary(got, (q0, q1), np.kron(B, A))
+        assert np.max(np.abs(got - ref)) < 1e-15, (q0, q1)
+
+
+def test_unitary_cnot_matrix_is_the_controlled_x():
+    """The 4x4 CNOT (control q0, target q1; local index b_q0 + 2 b_q1) equals
+    the controlled gate of Algorithm 1's caption with Q = X."""
+    cnot = np.zeros((4, 4))
+    cnot[0, 0] = cnot[2, 2] = cnot[3, 1] = cnot[1, 3] = 1.0
+    n = 5
+    for c, t in ((0, 3), (4, 1), (2, 3)):
+        psi = qc.random_state(n, 10 * c + t)
+        ref = psi.copy()
+        oracle.apply_ctrl(ref, c, t, qc.X_MATRIX)
+        got = psi.copy()
+        oracle.apply_unitary(got, (c, t), cnot)
+        assert np.array_equal(got, ref), (c, t)
+
+
+@pytest.mark.parametrize("qubits", [(2,), (0, 6), (5, 1), (3, 0, 6), (6, 2, 4, 1), (1, 5, 0, 3, 4)])
+def test_unitary_stride_tier_matches_dense_tier(qubits):
+    n = 7
+    u = qc.random_unitary(len(qubits), 100 + sum(qubits))
+    psi = qc.random_state(n, 55 + len(qubits))
+    ref = dense.operator_unitary(n, qubits, u) @ psi
+    got = psi.copy()
+    oracle.apply_unitary(got, qubits, u)
+    assert np.max(np.abs(got - ref)) < 1e-14
+    assert abs(oracle.norm(got) - 1.0) < 1e-13   # a unitary keeps the norm
+
+
+def test_unitary_qubit_order_permutes_the_matrix():
+    """Listing the qubits in another order is the same gate with its local
+    index bits permuted: U on (a, b) equals P U P on (b, a), P the swap of the
+    two local bits."""
+    n = 6
+    u = qc.random_unitary(2, 3)
+    P = np.eye(4)[[0, 2, 1, 3]]
+    psi = qc.random_state(n, 8)
+    a, b = psi.copy(), psi.copy()
+    oracle.apply_unitary(a, (1, 4), u)
+    oracle.apply_unitary(b, (4, 1), P @ u @ P)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_unitary_rejects_bad_qubits():
+    psi = qc.random_state(4, 1)
+    for q in ((1, 1), (4,), (-1,), (0, 1, 2, 3, 0)):
+        with pytest.raises(ValueError):
+            oracle.apply_unitary(psi, q, np.eye(1 << len(q)))
+
+
 def test_sampling_of_a_basis_state_and_of_the_uniform_state():
     """Measurement (section Quantum Circuits) of |x> always gives x; of the
     uniform state (H on every qubit, even n: every probability exactly 2^-n,

@@ -27,6 +27,12 @@ MUTANTS = {
     "qft_no_bit_reversal": [("<< (n - 1 - b);", "<< b;")],
     "norm_drops_imag": [("+ psi[2 * i + 1] * psi[2 * i + 1];", ";")],
     "mcu_any_control": [("if ((k & cmask) == cmask)", "if (k & cmask)")],
+    "unitary_transposed": [("double ur = U[2 * (r * D + c)], ui = U[2 * (r * D + c) + 1];",
+                            "double ur = U[2 * (c * D + r)], ui = U[2 * (c * D + r) + 1];")],
+    "unitary_qubits_reversed": [("off[c] |= (uint64_t)1 << q[m];",
+                                 "off[c] |= (uint64_t)1 << q[k - 1 - m];")],
+    "unitary_conjugated": [("im += ur * a[2 * c + 1] + ui * a[2 * c];",
+                            "im += ur * a[2 * c + 1] - ui * a[2 * c];")],
 }
 
 PINS = [
@@ -43,6 +49,10 @@ PINS = [
     pins.test_controlled_gate_leaves_control_zero_half_untouched,
     pins.test_toffoli_truth_table,
     lambda: pins.test_mcu_stride_tier_matches_dense_tier((0, 2, 4), 5),
+    pins.test_unitary_on_one_qubit_is_the_stride_update,
+    pins.test_unitary_tensor_product_of_one_qubit_gates,
+    pins.test_unitary_cnot_matrix_is_the_controlled_x,
+    lambda: pins.test_unitary_stride_tier_matches_dense_tier((6, 2, 4, 1)),
 ]
 
 
