@@ -152,6 +152,21 @@ sv_status sv_apply_ctrl(sv_state s, int control, int target, const double m[8]);
  * One pass over the amplitudes whose control bits are all set. */
 sv_status sv_apply_mcu(sv_state s, uint64_t control_mask, int target, const double m[8]);
 
+/* Applies a general gate on k qubits, 1 <= k <= 5: the 2^k x 2^k complex
+ * matrix u (row major, (re, im) interleaved FP64, 2 * 4^k doubles, read during
+ * the call) acting on the factor of qubits[0..k-1] in the tensor product of
+ * section Quantum Information Processing. For every setting of the other index
+ * bits, the amplitudes a_c, c = sum_m b_{qubits[m]} 2^m, become
+ * sum_c u[r][c] a_c, so qubits[0] is the least significant bit of the local
+ * index (u = B (x) A applies A to qubits[0] and B to qubits[1]). The qubits
+ * must be distinct and in [0, n); u is not checked for unitarity. k = 1 is
+ * sv_apply_1q. For k >= 2 and n >= 9 the gate is one dense 5-qubit block on
+ * the matrix cores (u padded with the identity on unused high qubits; one pass
+ * over the state); below 9 qubits a small-register kernel applies it. Errors:
+ * SV_EINVAL for a null pointer, k out of range, a repeated or out-of-range
+ * qubit. */
+sv_status sv_apply_unitary(sv_state s, const int32_t *qubits, int32_t k, const double *u);
+
 /* Controlled phase diag(1, e^{i theta}) on (control, target); symmetric in the
  * two qubits. The phase e^{i theta} is formed in FP64 for both dtypes. */
 sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
-    "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_cphase",
+    "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
     "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
@@ -75,6 +75,7 @@ _SIGNATURES = {
     "sv_apply_1q": ([_vp, _int, _dp], _int),
     "sv_apply_ctrl": ([_vp, _int, _int, _dp], _int),
     "sv_apply_mcu": ([_vp, ctypes.c_uint64, _int, _dp], _int),
+    "sv_apply_unitary": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _dp], _int),
     "sv_reset_uniform": ([_vp], _int),
     "sv_sample_device": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
@@ -203,6 +204,17 @@ def sv_apply_mcu(h: int, controls, target: int, m) -> None:
     for c in controls:
         mask |= 1 << int(c)
     _check(lib().sv_apply_mcu(h, mask, target, _mat(m)))
+
+
+def sv_apply_unitary(h: int, qubits, u) -> None:
+    """General gate: the 2^k x 2^k complex matrix u on `qubits` (k <= 5),
+    qubits[0] the least significant bit of the local index."""
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    m = np.ascontiguousarray(u, dtype=np.complex128)
+    if m.shape != (1 << len(q), 1 << len(q)):
+        raise ValueError("u must be 2^k x 2^k for k qubits")
+    _check(lib().sv_apply_unitary(h, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(q),
+                                  m.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
 def sv_apply_cphase(h: int, control: int, target: int, theta: float) -> None:
@@ -383,6 +395,9 @@ class StateVector:
 
     def apply_mcu(self, controls, target, m):
         sv_apply_mcu(self.handle, controls, target, m)
+
+    def apply_unitary(self, qubits, u):
+        sv_apply_unitary(self.handle, qubits, u)
 
     def apply_cphase(self, control, target, theta):
         sv_apply_cphase(self.handle, control, target, theta)

@@ -19,4 +19,17 @@ struct DenseArgs {
 // Requires n >= 9 (at least 16 columns).
 hipError_t launch_dense5(const DenseArgs &a, bool c64, hipStream_t st);
 
+// A general gate on k <= 5 qubits of a small register (one work-group per
+// setting of the other bits; used below 9 qubits, where k_dense5 has too few
+// columns).
+struct SmallUArgs {
+    void *psi;
+    const void *mat;     // 2^k x 2^k complex, row major, FP64 (re, im)
+    uint64_t omask;      // the other index bits
+    uint64_t ngroups;    // 2^(n-k)
+    uint64_t off[32];    // index offset of local combination c (q_0 = bit 0 of c)
+    int32_t dim;         // 2^k
+};
+hipError_t launch_unitary_small(const SmallUArgs &a, bool c64, hipStream_t st);
+
 }  // namespace svk

@@ -107,6 +107,41 @@ __global__ __launch_bounds__(256) void k_dense5(DenseArgs a)
     }
 }
 
+// Small registers: work-group g gathers the 2^k amplitudes of its setting of
+// the other bits into LDS, thread r forms output r = sum_c U[r][c] x_c in FP64
+// and writes it back after every input has been read.
+template <bool C64>
+__global__ __launch_bounds__(64) void k_unitary_small(SmallUArgs a)
+{
+    using A2 = std::conditional_t<C64, fv2, dv2>;
+    __shared__ dv2 x[32];
+    A2 *psi = static_cast<A2 *>(a.psi);
+    const dv2 *mat = static_cast<const dv2 *>(a.mat);
+    const int r = threadIdx.x;
+    for (uint64_t g = blockIdx.x; g < a.ngroups; g += gridDim.x) {
+        const uint64_t base = deposit(g, a.omask);
+        if (r < a.dim) {
+            const A2 v = psi[base | a.off[r]];
+            x[r] = dv2{double(v.x), double(v.y)};
+        }
+        __syncthreads();
+        if (r < a.dim) {
+            double re = 0.0, im = 0.0;
+            for (int c = 0; c < a.dim; ++c) {
+                const dv2 u = mat[r * a.dim + c];
+                re += u.x * x[c].x - u.y * x[c].y;
+                im += u.x * x[c].y + u.y * x[c].x;
+            }
+            using R = std::conditional_t<C64, float, double>;
+            A2 y;
+            y.x = R(re);
+            y.y = R(im);
+            psi[base | a.off[r]] = y;
+        }
+        __syncthreads();
+    }
+}
+
 int cus()
 {
     static int n = 0;
@@ -132,6 +167,17 @@ hipError_t launch_dense5(const DenseArgs &a, bool c64, hipStream_t st)
         hipLaunchKernelGGL(k_dense5<true>, dim3(grid), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_dense5<false>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_unitary_small(const SmallUArgs &a, bool c64, hipStream_t st)
+{
+    if (a.dim < 1 || a.dim > 32 || a.ngroups == 0) return hipErrorInvalidValue;
+    const unsigned grid = unsigned(a.ngroups < 4096 ? a.ngroups : 4096);
+    if (c64)
+        hipLaunchKernelGGL(k_unitary_small<true>, dim3(grid), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_unitary_small<false>, dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

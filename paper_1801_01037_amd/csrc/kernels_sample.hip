@@ -177,9 +177,10 @@ template <bool C64>
 __global__ __launch_bounds__(kThreads) void k_fill(void *psi, uint64_t count, double value)
 {
     using A = std::conditional_t<C64, float2, double2>;
+    using R = std::conditional_t<C64, float, double>;
     A v;
-    v.x = decltype(v.x)(value);
-    v.y = 0;
+    v.x = R(value);
+    v.y = R(0);
     A *p = static_cast<A *>(psi);
     for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < count;
          i += uint64_t(gridDim.x) * kThreads)

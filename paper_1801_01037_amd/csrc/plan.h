@@ -12,6 +12,12 @@ namespace svk {
 sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
                    std::string *err);
 
+// Queues a general gate U (2^k x 2^k complex, row major, FP64) on the k
+// validated, distinct qubits q[0..k-1], 2 <= k <= 5: as one dense 5-qubit
+// block on the matrix cores when n >= 9 (U padded with the identity on the
+// highest unused qubits), else with the small-register kernel.
+sv_status apply_unitary(sv_state s, const int32_t *q, int k, const double *u, std::string *err);
+
 // Frees planning buffers and cached graphs owned by the handle.
 void plan_release(sv_state s);
 

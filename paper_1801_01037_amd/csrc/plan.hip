@@ -1202,6 +1202,90 @@ static sv_status run_dense(sv_state s, const sv_gate *gates, size_t n_gates, std
     return SV_OK;
 }
 
+sv_status apply_unitary(sv_state s, const int32_t *q, int k, const double *u, std::string *err)
+{
+    const bool c64 = s->dt == SV_C64;
+    const int dim = 1 << k;
+    const uint64_t all = (uint64_t(1) << s->n) - 1;
+    uint64_t qm = 0;
+    for (int m = 0; m < k; ++m) qm |= uint64_t(1) << q[m];
+    if (s->n < 9) {
+        char *d = nullptr;
+        const size_t bytes = size_t(dim) * dim * 2 * sizeof(double);
+        sv_status st = stage_upload(s, bytes, [&](char *h) { std::memcpy(h, u, bytes); }, &d, err);
+        if (st != SV_OK) return st;
+        SmallUArgs a{};
+        a.psi = s->psi;
+        a.mat = d;
+        a.omask = all & ~qm;
+        a.ngroups = uint64_t(1) << (s->n - k);
+        a.dim = dim;
+        for (int c = 0; c < dim; ++c) {
+            a.off[c] = 0;
+            for (int m = 0; m < k; ++m)
+                if ((c >> m) & 1) a.off[c] |= uint64_t(1) << q[m];
+        }
+        const int tok = prof_begin(s);
+        hipError_t e = launch_unitary_small(a, c64, s->stream);
+        prof_end(s, tok, KC_DENSE, 2.0 * std::ldexp(1.0, s->n) * elem_bytes(s->dt),
+                 8.0 * dim * std::ldexp(1.0, s->n));
+        if (e != hipSuccess) { *err = std::string("unitary launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
+        return SV_OK;
+    }
+    // Pad to five qubits with the highest unused ones (the low index bits stay
+    // in the column index), then write U in the block's ascending bit order:
+    // block row R holds U[r][c] when the padding bits of R and C agree.
+    uint64_t bm = qm;
+    for (int b = s->n - 1; b >= 0 && popcount64(bm) < 5; --b) bm |= uint64_t(1) << b;
+    int pos[64];
+    for (int b = 0, j = 0; b < 64; ++b)
+        if ((bm >> b) & 1) pos[b] = j++;
+    int lbit[5];                 // block bit of local bit m of U
+    uint32_t padm = 0;           // block bits that are padding
+    for (int m = 0; m < k; ++m) lbit[m] = pos[q[m]];
+    for (int b = 0; b < 64; ++b)
+        if (((bm >> b) & 1) && !((qm >> b) & 1)) padm |= 1u << pos[b];
+    auto local = [&](int R) {
+        int r = 0;
+        for (int m = 0; m < k; ++m) r |= ((R >> lbit[m]) & 1) << m;
+        return r;
+    };
+    const size_t mat_bytes = 64 * 64 * (c64 ? sizeof(float) : sizeof(double));
+    auto fill = [&](char *h) {
+        for (int R = 0; R < 32; ++R)
+            for (int C = 0; C < 32; ++C) {
+                double re = 0.0, im = 0.0;
+                if ((R & padm) == (C & padm)) {
+                    const int r = local(R), c = local(C);
+                    re = u[2 * (r * dim + c)];
+                    im = u[2 * (r * dim + c) + 1];
+                }
+                const double v[4] = {re, -im, im, re};   // [[Re, -Im], [Im, Re]]
+                const int idx[4] = {R * 64 + C, R * 64 + 32 + C, (32 + R) * 64 + C,
+                                    (32 + R) * 64 + 32 + C};
+                for (int z = 0; z < 4; ++z) {
+                    if (c64) reinterpret_cast<float *>(h)[idx[z]] = float(v[z]);
+                    else reinterpret_cast<double *>(h)[idx[z]] = v[z];
+                }
+            }
+    };
+    char *d = nullptr;
+    sv_status st = stage_upload(s, mat_bytes, fill, &d, err);
+    if (st != SV_OK) return st;
+    DenseArgs a{};
+    a.psi = s->psi;
+    a.mat = d;
+    a.bmask = bm;
+    a.omask = all & ~bm;
+    a.ncols = uint64_t(1) << (s->n - 5);
+    const double N = std::ldexp(1.0, s->n);
+    const int tok = prof_begin(s);
+    hipError_t e = launch_dense5(a, c64, s->stream);
+    prof_end(s, tok, KC_DENSE, 2.0 * N * elem_bytes(s->dt), 256.0 * N);
+    if (e != hipSuccess) { *err = std::string("dense launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
+    return SV_OK;
+}
+
 sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
                    std::string *err)
 {

@@ -219,7 +219,7 @@ bool is_phase_diag(const double m[8])
 
 extern "C" {
 
-int sv_version(void) { return 2; }
+int sv_version(void) { return 3; }
 
 const char *sv_last_error(void) { return g_err.c_str(); }
 
@@ -353,6 +353,30 @@ sv_status sv_apply_mcu(sv_state s, uint64_t control_mask, int target, const doub
     if (sv_status st = validate_gate(s, g, 0)) return st;
     DeviceScope ds(s->device);
     return queue_gate(s, g);
+}
+
+sv_status sv_apply_unitary(sv_state s, const int32_t *qubits, int32_t k, const double *u)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (!qubits || !u) return fail(SV_EINVAL, "null qubit list or matrix");
+    if (k < 1 || k > 5 || k > s->n) return fail(SV_EINVAL, "k = %d not in [1, min(5, n)]", k);
+    uint64_t seen = 0;
+    for (int m = 0; m < k; ++m) {
+        if (qubits[m] < 0 || qubits[m] >= s->n)
+            return fail(SV_EINVAL, "qubit %d out of range [0, %d)", qubits[m], s->n);
+        if ((seen >> qubits[m]) & 1) return fail(SV_EINVAL, "qubit %d listed twice", qubits[m]);
+        seen |= uint64_t(1) << qubits[m];
+    }
+    DeviceScope ds(s->device);
+    if (k == 1) {   // the pair update itself
+        sv_gate g{SV_G_U, -1, qubits[0], 0, {}};
+        std::memcpy(g.m, u, sizeof g.m);
+        return queue_gate(s, g);
+    }
+    std::string err;
+    sv_status st = svk::apply_unitary(s, qubits, k, u, &err);
+    if (st != SV_OK) return fail(st, "%s", err.c_str());
+    return SV_OK;
 }
 
 sv_status sv_apply_cphase(sv_state s, int control, int target, double theta)

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version(lib):
-    assert sv.sv_version() == 2
+    assert sv.sv_version() == 3
 
 
 def test_rejects_bad_arguments_without_a_device(lib):
