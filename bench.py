@@ -8,6 +8,9 @@ One step runs the whole hot path once over the 30-qubit workload:
 The state lives in HBM the whole time (complex128: 16 GiB; complex64: 8 GiB).
 `value` is gates per second over the timed steps in complex128 (the paper's
 precision); the complex64 run of the same steps is reported beside it.
+Beside the steps (untimed for `value`): a batch of 512 circuits (p50/p99
+latency), serving samples at the offered rates of --serving-rates, and the
+oracle on the host cores as the CPU baseline.
 
 Printed: ONE JSON line on stdout. Diagnostics go to stderr.
 """
@@ -52,8 +55,10 @@ def parse():
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-circuits", type=int, default=512)
-    ap.add_argument("--serving-arrivals", type=int, default=0,
-                    help="also run a short serving sample with this many arrivals")
+    ap.add_argument("--serving-arrivals", type=int, default=64,
+                    help="arrivals of each serving sample (0: no serving sample)")
+    ap.add_argument("--serving-rates", default="100,1000",
+                    help="offered request rates (per second) of the serving samples")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a plain copy kernel of "
                          "known size, for scaling memory-traffic counters)")
@@ -300,8 +305,12 @@ def main():
         log(f"[bench] batched p50 {batched['p50_ms']} ms p99 {batched['p99_ms']} ms")
     serving_stats = None
     if args.serving_arrivals:
-        log(f"[bench] serving: {args.serving_arrivals} arrivals")
-        serving_stats = run_serving(args.serving_arrivals)
+        serving_stats = []
+        for rate in [float(r) for r in args.serving_rates.split(",") if r]:
+            log(f"[bench] serving: {args.serving_arrivals} arrivals at {rate:g}/s")
+            serving_stats.append(run_serving(args.serving_arrivals, rate))
+            log(f"[bench] serving p50 {serving_stats[-1].get('p50_ms')} ms "
+                f"p99 {serving_stats[-1].get('p99_ms')} ms")
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
