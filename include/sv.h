@@ -252,6 +252,15 @@ sv_status sv_batch_destroy(sv_batch b);
 /* Tuning: work-groups per CU of each level launch (1..8, default 2) and tiles
  * per task (1..4096, default 8). */
 sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task);
+/* Persistent launch for small circuits: a circuit whose passes have at most
+ * max_tiles tiles (2^(n-12) for n > 12, one below) runs whole, every pass in
+ * order, on the one work-group that takes it from a queue counter; one launch
+ * covers all of them, ahead of the levels of the larger circuits. No
+ * work-group ever waits for another (between passes a work-group only fences
+ * its own stores and meets its own waves), so the launch ends once the queue
+ * is empty. Results are bit for bit those of the level launches. max_tiles =
+ * 0 (the default) turns it off; at most 2^20. */
+sv_status sv_batch_persist(sv_batch b, int32_t max_tiles);
 /* Queues passes [first_pass[i], first_pass[i] + pass_count[i]) of plans[i],
  * i < count, on the batch's stream (first_pass NULL: from 0; pass_count NULL:
  * to the end). The plans' states must be distinct and of the batch's dtype;

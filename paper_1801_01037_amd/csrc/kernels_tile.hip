@@ -536,6 +536,44 @@ __global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
     }
 }
 
+// Persistent launch over whole small circuits (see PersistArgs): work-group
+// w runs circuits w, w + G, w + 2G, ... (G work-groups), every pass of each in
+// order. The loop index is uniform and its trip count fixed, and no
+// work-group waits for another. (Taking circuits from a shared queue counter,
+// with one lane doing the atomic add and the index broadcast through LDS,
+// made the compiler split this loop around that lane: the other lanes then
+// ran the same circuit again without end.)
+template <bool C64, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_persist(PersistArgs p)
+{
+    using A = AmpT<C64>;
+    constexpr int K = 4;
+    A *lds = lds_base<C64>();
+    const PersistCircuit SV_CONST *circs = (const PersistCircuit SV_CONST *)(p.circs);
+    const TileArgs SV_CONST *passes = (const TileArgs SV_CONST *)(p.passes);
+    for (uint32_t c = blockIdx.x; c < p.count; c += gridDim.x) {
+        const int32_t pass0 = circs[c].pass0, npass = circs[c].npass;
+        if (threadIdx.x == 0) p.t_start[c] = wall_clock64();
+        for (int32_t k = 0; k < npass; ++k) {
+            const TileArgs SV_CONST &pc = passes[pass0 + k];
+            TileArgs a;
+            a.psi = pc.psi; a.groups = pc.groups; a.ops = pc.ops; a.dtab = pc.dtab;
+            a.phase_tab = pc.phase_tab; a.tmask = pc.tmask; a.omask = pc.omask; a.ntiles = pc.ntiles;
+            a.L = pc.L; a.nlow = pc.nlow; a.nnon = pc.nnon; a.group0 = pc.group0;
+            a.ngroups = pc.ngroups; a.has_diag = pc.has_diag; a.permute = pc.permute; a.osrc = pc.osrc;
+            const uint32_t size = 1u << a.L;
+            A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+            run_tiles<C64, K>(a, 0, a.ntiles, 1, lds, tab);
+            // The next pass loads what this one stored, from other waves of
+            // the work-group: release the stores, meet, acquire.
+            __threadfence();
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (threadIdx.x == 0) p.t_end[c] = wall_clock64();
+    }
+}
+
 int cu_count()
 {
     static int cus = 0;
@@ -591,6 +629,24 @@ hipError_t launch_dt(const TileArgs &a, int K, size_t lds, hipStream_t st)
 }
 
 }  // namespace
+
+hipError_t launch_persist(const PersistArgs &p, bool c64, int blocks_per_cu, hipStream_t st)
+{
+    if (p.count == 0) return hipSuccess;
+    const int threads = c64 ? (1 << (kTileL64 - 4)) : (1 << (kTileL128 - 4));
+    const size_t lds = tile_lds_bytes(c64, c64 ? kTileL64 : kTileL128, true);
+    const uint32_t want = uint32_t(cu_count() * (blocks_per_cu > 0 ? blocks_per_cu : 2));
+    const unsigned grid = p.count < want ? p.count : want;
+    hipError_t e;
+    if (c64) {
+        if ((e = set_max_lds(k_persist<true, 256>, true)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_persist<true, 256>), dim3(grid), dim3(threads), lds, st, p);
+    } else {
+        if ((e = set_max_lds(k_persist<false, 256>, false)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_persist<false, 256>), dim3(grid), dim3(threads), lds, st, p);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_tile(const TileArgs &a, int K, bool c64, hipStream_t st)
 {

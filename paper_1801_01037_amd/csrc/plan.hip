@@ -1405,6 +1405,10 @@ struct BatchImage {
     std::vector<uint32_t> level0;      // first task of each level, plus the end
     std::vector<int32_t> task_circ;    // circuit of each task
     size_t count = 0;                  // circuits
+    // Circuits run whole by the persistent launch (before the levels):
+    // circuit index of each entry, and where its table and clocks sit in `dev`.
+    std::vector<int32_t> pcirc;
+    size_t off_circ = 0, off_pstart = 0, off_pend = 0;
 };
 
 struct sv_batch_s {
@@ -1413,6 +1417,8 @@ struct sv_batch_s {
     hipStream_t capture = nullptr;     // private stream for graph capture
     int blocks_per_cu = 2;
     uint32_t tiles_per_task = 8;
+    int32_t persist_tiles = 0;         // circuits of at most this many tiles per pass
+                                       // run whole in the persistent launch (0: none)
     BatchImage work;                   // runs without SV_GRAPH
     BatchImage gimg;                   // the captured graph's own buffers
     hipGraphExec_t gexec = nullptr;
@@ -1563,6 +1569,14 @@ sv_status sv_batch_destroy(sv_batch b)
     return SV_OK;
 }
 
+sv_status sv_batch_persist(sv_batch b, int32_t max_tiles)
+{
+    if (!b) return berr(SV_EINVAL, "null batch");
+    if (max_tiles < 0 || max_tiles > (1 << 20)) return berr(SV_EINVAL, "max_tiles out of range");
+    b->persist_tiles = max_tiles;
+    return SV_OK;
+}
+
 sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task)
 {
     if (!b) return berr(SV_EINVAL, "null batch");
@@ -1623,6 +1637,22 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     const uint64_t cap = uint64_t(device_cus()) * uint64_t(std::max(1, b->blocks_per_cu)) *
                          uint64_t(b->tiles_per_task) * 2 * (uint64_t(1) << 12);
     std::vector<int32_t> done(count, 0);
+    // Small circuits go whole to the persistent launch, least work first.
+    std::vector<PersistCircuit> circs;
+    img.pcirc.clear();
+    if (b->persist_tiles > 0) {
+        std::vector<size_t> small;
+        for (size_t i = 0; i < count; ++i)
+            if (cnt[i] > 0 && passes[pass0[i]].ntiles <= uint64_t(b->persist_tiles)) small.push_back(i);
+        std::stable_sort(small.begin(), small.end(), [&](size_t x, size_t y) {
+            return uint64_t(cnt[x]) * amps[x] < uint64_t(cnt[y]) * amps[y];
+        });
+        for (size_t i : small) {
+            circs.push_back(PersistCircuit{int32_t(pass0[i]), cnt[i]});
+            img.pcirc.push_back(int32_t(i));
+            done[i] = cnt[i];
+        }
+    }
     std::vector<size_t> order;
     order.reserve(count);
     for (;;) {
@@ -1655,9 +1685,12 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     img.level0.push_back(uint32_t(tasks.size()));
     img.count = count;
     img.off_pass = align_up(tasks.size() * sizeof(BatchTask), 256);
-    img.off_start = align_up(img.off_pass + passes.size() * sizeof(TileArgs), 256);
+    img.off_circ = align_up(img.off_pass + passes.size() * sizeof(TileArgs), 256);
+    img.off_start = align_up(img.off_circ + circs.size() * sizeof(PersistCircuit), 256);
     img.off_end = align_up(img.off_start + tasks.size() * sizeof(uint64_t), 256);
-    const size_t total = align_up(img.off_end + tasks.size() * sizeof(uint64_t), 256);
+    img.off_pstart = align_up(img.off_end + tasks.size() * sizeof(uint64_t), 256);
+    img.off_pend = align_up(img.off_pstart + circs.size() * sizeof(uint64_t), 256);
+    const size_t total = align_up(img.off_pend + circs.size() * sizeof(uint64_t), 256);
     const size_t upload = img.off_start;
     hipError_t e = hipEventSynchronize(b->staged);   // staging free again
     if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
@@ -1681,17 +1714,29 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     char *h = static_cast<char *>(b->host);
     std::memcpy(h, tasks.data(), tasks.size() * sizeof(BatchTask));
     std::memcpy(h + img.off_pass, passes.data(), passes.size() * sizeof(TileArgs));
+    std::memcpy(h + img.off_circ, circs.data(), circs.size() * sizeof(PersistCircuit));
     e = hipMemcpyAsync(img.dev, h, upload, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(b->staged, st);
     if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
     return SV_OK;
 }
 
-// Queues one launch per level of `img` on `st`.
+// Queues the persistent launch (if any circuit takes it) and one launch per
+// level of `img` on `st`.
 sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
 {
     using namespace svk;
     char *d = static_cast<char *>(img.dev);
+    if (!img.pcirc.empty()) {
+        PersistArgs p{};
+        p.circs = reinterpret_cast<const PersistCircuit *>(d + img.off_circ);
+        p.passes = reinterpret_cast<const TileArgs *>(d + img.off_pass);
+        p.t_start = reinterpret_cast<uint64_t *>(d + img.off_pstart);
+        p.t_end = reinterpret_cast<uint64_t *>(d + img.off_pend);
+        p.count = uint32_t(img.pcirc.size());
+        hipError_t e = launch_persist(p, b->dt == SV_C64, b->blocks_per_cu, st);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("persistent launch: ") + hipGetErrorString(e));
+    }
     BatchArgs a{};
     a.tasks = reinterpret_cast<const BatchTask *>(d);
     a.passes = reinterpret_cast<const TileArgs *>(d + img.off_pass);
@@ -1721,6 +1766,7 @@ sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pa
     key.reserve(3 * count + 2);
     key.push_back(uintptr_t(b->blocks_per_cu));
     key.push_back(uintptr_t(b->tiles_per_task));
+    key.push_back(uintptr_t(b->persist_tiles));
     for (size_t i = 0; i < count; ++i) {
         const sv_plan p = plans[i];
         if (!p) return berr(SV_EINVAL, "null plan in batch");
@@ -1783,24 +1829,35 @@ sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t co
     if (!b) return berr(SV_EINVAL, "null batch");
     const BatchImage *img = b->last;
     if (!img || count != img->count) return berr(SV_EINVAL, "count differs from the last run");
-    const size_t nt = img->task_circ.size();
-    std::vector<uint64_t> t0(nt), t1(nt);
+    const size_t nt = img->task_circ.size(), np = img->pcirc.size();
+    // Task clocks, then the persistent circuits' clocks, as one list.
+    std::vector<uint64_t> t0(nt + np), t1(nt + np);
+    std::vector<int32_t> circ_of(img->task_circ);
+    circ_of.insert(circ_of.end(), img->pcirc.begin(), img->pcirc.end());
     hipError_t e = hipSuccess;
+    char *dev = static_cast<char *>(img->dev);
     if (nt) {
-        e = hipMemcpyAsync(t0.data(), static_cast<char *>(img->dev) + img->off_start,
-                           nt * sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream);
+        e = hipMemcpyAsync(t0.data(), dev + img->off_start, nt * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, b->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(t1.data(), static_cast<char *>(img->dev) + img->off_end,
-                               nt * sizeof(uint64_t), hipMemcpyDeviceToHost, b->stream);
+            e = hipMemcpyAsync(t1.data(), dev + img->off_end, nt * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, b->stream);
+    }
+    if (np && e == hipSuccess) {
+        e = hipMemcpyAsync(t0.data() + nt, dev + img->off_pstart, np * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t1.data() + nt, dev + img->off_pend, np * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, b->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
     const int khz = svk::wall_clock_khz();
     uint64_t origin = ~uint64_t(0);
-    for (size_t k = 0; k < nt; ++k) origin = std::min(origin, t0[k]);
+    for (size_t k = 0; k < nt + np; ++k) origin = std::min(origin, t0[k]);
     std::vector<uint64_t> first(count, ~uint64_t(0)), last(count, 0);
-    for (size_t k = 0; k < nt; ++k) {
-        const int32_t c = img->task_circ[k];
+    for (size_t k = 0; k < nt + np; ++k) {
+        const int32_t c = circ_of[k];
         first[c] = std::min(first[c], t0[k]);
         last[c] = std::max(last[c], t1[k]);
     }

@@ -122,4 +122,23 @@ struct BatchArgs {
 // the dtype), blocks_per_cu work-groups per CU taking tasks round-robin.
 hipError_t launch_level(const BatchArgs &b, bool c64, int blocks_per_cu, hipStream_t st);
 
+// One circuit of a persistent launch: passes [pass0, pass0 + npass) of
+// PersistArgs.passes, all run in order by the one work-group that takes it.
+struct PersistCircuit {
+    int32_t pass0, npass;
+};
+
+// A persistent launch over small circuits: work-group w runs circuits w,
+// w + G, ... (G work-groups), all passes of each, every tile of each pass,
+// with a fence and a work-group barrier between passes. No work-group waits
+// for another; each leaves after its last circuit.
+struct PersistArgs {
+    const PersistCircuit *circs;
+    const TileArgs *passes;
+    uint64_t *t_start;          // per circuit: device clock when its first pass started
+    uint64_t *t_end;            // per circuit: when its last pass ended
+    uint32_t count;
+};
+hipError_t launch_persist(const PersistArgs &p, bool c64, int blocks_per_cu, hipStream_t st);
+
 }  // namespace svk

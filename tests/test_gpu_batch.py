@@ -206,3 +206,80 @@ def test_expired_waits_are_reported_and_the_launch_ends():
         sv.sv_plan_destroy(p)
         sv.sv_destroy(h)
     assert np.array_equal(got, _run_alone(n, dtype, g))
+
+
+# ---- the persistent launch for small circuits ---------------------------------
+
+@pytest.mark.parametrize("max_tiles", [1, 16, 1 << 20], ids=["one-tile", "up-to-16", "all"])
+@pytest.mark.parametrize("flags", [0, sv.SV_GRAPH], ids=["launches", "graph"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
+def test_persistent_batch_equals_alone(dtype, flags, max_tiles):
+    """Circuits small enough run whole in one persistent launch (the rest in
+    levels after it); every result equals the circuit run alone, bit for bit,
+    also on a graph replay (the queue counter is cleared by a kernel in the
+    graph), and every circuit's clock interval is filled."""
+    specs = _specs(20, 21, 4, 17, 5, 60)
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_persist(b, max_tiles)
+        sv.sv_batch_run(b, plans, flags=flags)
+        start, end = sv.sv_batch_times(b, len(plans))
+        outs = [sv.sv_copy_out(h) for h in states]
+        if flags:
+            for h in states:
+                sv.sv_reset(h, 0)
+                sv.sv_synchronize(h)
+            sv.sv_batch_run(b, plans, flags=flags)
+            sv.sv_batch_times(b, len(plans))
+            again = [sv.sv_copy_out(h) for h in states]
+            assert all(np.array_equal(x, y) for x, y in zip(outs, again))
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    assert np.all(end > start) and np.all(start >= 0)
+    for (n, d, s), g, got in zip(specs, circuits, outs):
+        assert np.array_equal(got, _run_alone(n, dtype, g)), (n, d)
+        if n <= 12:
+            assert_close(got, oracle.simulate(n, g), dtype, len(g), f"persistent n={n} d={d}")
+
+
+def test_persistent_small_circuits_finish_first():
+    """With the persistent launch, the small circuits of a batch end before
+    the first level of the large one has run."""
+    dtype = sv.SV_C64
+    specs = [(22, 20, 31)] + [(10, 30, 40 + i) for i in range(32)]
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_persist(b, 1)
+        sv.sv_batch_run(b, plans)
+        start, end = sv.sv_batch_times(b, len(plans))
+        outs = [sv.sv_copy_out(h) for h in states]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    assert max(end[1:]) <= start[0], (start[0], max(end[1:]))
+    for (n, d, s), g, got in zip(specs[1:], circuits[1:], outs[1:]):
+        assert np.array_equal(got, _run_alone(n, dtype, g))
+
+
+def test_persist_rejects_bad_values():
+    b = sv.sv_batch_create(sv.SV_C64)
+    try:
+        for v in (-1, (1 << 20) + 1):
+            with pytest.raises(sv.SVError) as e:
+                sv.sv_batch_persist(b, v)
+            assert e.value.status == sv.SV_EINVAL
+    finally:
+        sv.sv_batch_destroy(b)
