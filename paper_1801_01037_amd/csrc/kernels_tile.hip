@@ -190,6 +190,99 @@ __device__ __forceinline__ void apply_pair(const Amps<C64, K> &in, Amps<C64, K> 
     }
 }
 
+// A 2x2 (or an exchange) on register position PJ controlled by register
+// position PC: only the pairs whose PC bit is set are updated, the others
+// are copied; with both positions fixed at compile time an exchange is a
+// plain register permutation.
+template <bool C64, int K, int PJ, int PC, bool SWAP>
+__device__ __forceinline__ void pair_rc(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
+{
+    using R = RealT<C64>;
+    using A = AmpT<C64>;
+    constexpr int NR = 1 << K;
+    constexpr int bj = 1 << PJ, bc = 1 << PC;
+    R m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0, m6 = 0, m7 = 0;
+    if constexpr (!SWAP) {
+        if constexpr (C64) {
+            m0 = op.mf[0]; m1 = op.mf[1]; m2 = op.mf[2]; m3 = op.mf[3];
+            m4 = op.mf[4]; m5 = op.mf[5]; m6 = op.mf[6]; m7 = op.mf[7];
+        } else {
+            m0 = op.m[0]; m1 = op.m[1]; m2 = op.m[2]; m3 = op.m[3];
+            m4 = op.m[4]; m5 = op.m[5]; m6 = op.m[6]; m7 = op.m[7];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r & bj) continue;
+        const int r1 = r | bj;
+        if (!(r & bc)) {
+            out[r] = in[r];
+            out[r1] = in[r1];
+            continue;
+        }
+        const A a = in[r], b = in[r1];
+        if constexpr (SWAP) {
+            out[r] = b;
+            out[r1] = a;
+        } else {
+            A na, nb;
+            na.x = fmadd(-m3, b.y, fmadd(m2, b.x, fmadd(-m1, a.y, m0 * a.x)));
+            na.y = fmadd(m3, b.x, fmadd(m2, b.y, fmadd(m1, a.x, m0 * a.y)));
+            nb.x = fmadd(-m7, b.y, fmadd(m6, b.x, fmadd(-m5, a.y, m4 * a.x)));
+            nb.y = fmadd(m7, b.x, fmadd(m6, b.y, fmadd(m5, a.x, m4 * a.y)));
+            out[r] = na;
+            out[r1] = nb;
+        }
+    }
+}
+
+template <bool C64, int K, int PJ, bool SWAP>
+__device__ __forceinline__ void apply_rc_j(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
+{
+    // The planner sets pk (the control's register position) below K and
+    // different from pj; the other arms are unreachable.
+    switch (op.pk) {
+    case 0:
+        if constexpr (PJ != 0) pair_rc<C64, K, PJ, 0, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    case 1:
+        if constexpr (K > 1 && PJ != 1) pair_rc<C64, K, PJ, 1, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    case 2:
+        if constexpr (K > 2 && PJ != 2) pair_rc<C64, K, PJ, 2, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    case 3:
+        if constexpr (K > 3 && PJ != 3) pair_rc<C64, K, PJ, 3, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    default: __builtin_unreachable();
+    }
+}
+
+template <bool C64, int K, bool SWAP>
+__device__ __forceinline__ void apply_rc(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op)
+{
+    switch (op.pj) {
+    case 0: apply_rc_j<C64, K, 0, SWAP>(in, out, op); break;
+    case 1:
+        if constexpr (K > 1) apply_rc_j<C64, K, 1, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    case 2:
+        if constexpr (K > 2) apply_rc_j<C64, K, 2, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    case 3:
+        if constexpr (K > 3) apply_rc_j<C64, K, 3, SWAP>(in, out, op);
+        else __builtin_unreachable();
+        break;
+    default: __builtin_unreachable();
+    }
+}
+
 // A 4x4 unitary on register positions P0 < P1: each quad of amplitudes that
 // differ only in those two bits is multiplied by the matrix.
 template <bool C64, int K, int P0, int P1>
@@ -316,10 +409,12 @@ __device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &o
     } else if (op.octrl >= 0 && !((gbase >> op.octrl) & 1ull)) {
         copy_amps<C64, K>(in, out);
     } else if (op.kind == TOP_SWAP) {
-        if (op.lctrl >= 0) apply_pair<C64, K, true, true>(in, out, li, op);
+        if (op.pk >= 0) apply_rc<C64, K, true>(in, out, op);
+        else if (op.lctrl >= 0) apply_pair<C64, K, true, true>(in, out, li, op);
         else apply_pair<C64, K, true, false>(in, out, li, op);
     } else {
-        if (op.lctrl >= 0) apply_pair<C64, K, false, true>(in, out, li, op);
+        if (op.pk >= 0) apply_rc<C64, K, false>(in, out, op);
+        else if (op.lctrl >= 0) apply_pair<C64, K, false, true>(in, out, li, op);
         else apply_pair<C64, K, false, false>(in, out, li, op);
     }
 }

@@ -928,9 +928,15 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                 } else {
                     const int p = local(op.target);
                     to.pj = int(std::find(g.S.begin(), g.S.end(), p) - g.S.begin());
+                    to.pk = -1;
                     if (op.control >= 0) {
-                        if ((Tm >> op.control) & 1) to.lctrl = local(op.control);
-                        else to.octrl = op.control;
+                        if ((Tm >> op.control) & 1) {
+                            to.lctrl = local(op.control);
+                            const int pc = int(std::find(g.S.begin(), g.S.end(), to.lctrl) - g.S.begin());
+                            if (pc < geo.K) to.pk = pc;
+                        } else {
+                            to.octrl = op.control;
+                        }
                     }
                     std::memcpy(to.m, op.m, sizeof to.m);
                     for (int k = 0; k < 8; ++k) to.mf[k] = float(op.m[k]);

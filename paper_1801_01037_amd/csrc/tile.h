@@ -50,7 +50,9 @@ struct TileOp {
                        // TOP_DIAG: 1 if PR is not zero for every r
     int32_t lctrl;     // control as a local tile bit, or -1
     int32_t octrl;     // control as a global index bit outside the tile, or -1
-    int32_t pk;        // TOP_U4: the higher of its two positions
+    int32_t pk;        // TOP_U4: the higher of its two positions;
+                       // TOP_U / TOP_SWAP: the control's position in the
+                       // group's S when it is a register bit, else -1
     int32_t dthr;      // TOP_DIAG: offset (uint64 units) in the plan's table
                        // area of thr, 2^(L-K) rows of K+1 values
     int32_t dout;      // TOP_DIAG: offset of the byte tables, or -1 (none)
