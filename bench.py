@@ -46,9 +46,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate", "dense"], default="fused",
+    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl"], default="fused",
                     help="fused: SV_FUSE tile passes; pergate: one launch per gate; "
-                         "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores")
+                         "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores; "
+                         "sweep: per-gate timings on every qubit at 30 qubits; "
+                         "xl: the 33-qubit complex128 / 34-qubit complex64 depth-10 circuit")
+    ap.add_argument("--reps", type=int, default=20, help="timed repetitions per gate (sweep)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -251,6 +254,109 @@ def run_batched(sv, torch, count, seed=3):
             "persistent_small": persistent}
 
 
+def _event_times(torch, stream, fn, reps, warmup=3):
+    """Device times (ms) of `reps` calls of fn, each between two HIP events on
+    `stream`, after `warmup` untimed calls."""
+    for _ in range(warmup):
+        fn()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def _stats(ms, nbytes):
+    a = np.asarray(ms)
+    med = float(np.median(a))
+    return {"median_ms": round(med, 4), "min_ms": round(float(a.min()), 4),
+            "p90_ms": round(float(np.percentile(a, 90)), 4),
+            "GBps": round(nbytes / (med * 1e-3) / 1e9, 1)}
+
+
+def run_sweep(sv, torch, n, reps):
+    """Per-gate timings at n qubits: a Haar 2x2 on every qubit, CNOT on
+    neighbours and on (0, n-1) both ways, controlled phases, and general
+    5-qubit gates on fixed qubit sets (one dense block on the matrix cores).
+    Bytes are the algorithmic ones: 2 N s for a full pass, N s for a CNOT (the
+    control-1 half), N s / 2 for a controlled phase (the quarter with both bits
+    set)."""
+    import qcircuits as qc
+    out = {}
+    for dt, tag, sb in ((sv.SV_C128, "c128", 16), (sv.SV_C64, "c64", 8)):
+        N = 2.0 ** n
+        st = sv.StateVector(n, dt)
+        try:
+            u = qc.haar_su2(5, 1)[0]
+            one = {q: _stats(_event_times(torch, st.stream, lambda q=q: st.apply_1q(q, u), reps),
+                             2 * N * sb) for q in range(n)}
+            pairs = [(q, q + 1) for q in range(n - 1)] + [(0, n - 1), (n - 1, 0)]
+            cnot = {f"{c},{t}": _stats(_event_times(torch, st.stream,
+                                                    lambda c=c, t=t: st.apply_ctrl(c, t, qc.X_MATRIX), reps),
+                                       N * sb) for c, t in pairs}
+            cp = {f"{c},{t}": _stats(_event_times(torch, st.stream,
+                                                  lambda c=c, t=t: st.apply_cphase(c, t, 0.3), reps),
+                                     N * sb / 2) for c, t in ((0, n - 1), (n // 2 - 1, n // 2))}
+            blocks = {}
+            for qs in ((0, 1, 2, 3, 4), (12, 13, 14, 15, 16), tuple(range(n - 5, n)),
+                       (0, 7, 15, 22, n - 1)):
+                m = qc.random_unitary(5, sum(qs))
+                blocks[",".join(map(str, qs))] = _stats(
+                    _event_times(torch, st.stream, lambda qs=qs, m=m: st.apply_unitary(qs, m), reps),
+                    2 * N * sb)
+        finally:
+            st.close()
+            torch.cuda.empty_cache()
+        med1 = [v["median_ms"] for v in one.values()]
+        out[tag] = {"one_qubit": one, "cnot": cnot, "cphase": cp, "block5": blocks,
+                    "one_qubit_gates_per_s": round(1e3 / float(np.mean(med1)), 2)}
+        log(f"[bench] sweep {tag}: 1q median {min(med1):.3f}..{max(med1):.3f} ms")
+    return out
+
+
+def run_xl(sv, torch, reps=1):
+    """The 33-qubit complex128 and 34-qubit complex64 registers (128 GiB each):
+    a seeded depth-10 layered circuit with dense 5-qubit blocks
+    (SV_FUSE_DENSE), with tile passes (SV_FUSE) and gate by gate; each run is
+    followed by the inverse circuit in the same mode, and the distance from
+    |0...0> (max-abs over sampled indices and the amplitude at 0) and the norm
+    drift measure the error against exact arithmetic."""
+    import qcircuits as qc
+    out = {}
+    for n, dt, tag in ((33, sv.SV_C128, "c128_33q"), (34, sv.SV_C64, "c64_34q")):
+        g = qc.layer_circuit(n, 10, 1000 + n)
+        inv = qc.inverse_circuit(g)
+        st = sv.StateVector(n, dt)
+        res = {"gates": int(len(g))}
+        try:
+            idx = np.unique((qc.splitmix64(n, 4096) >> np.uint64(64 - n)).astype(np.int64))
+            idx = idx[idx != 0]
+            for name, flags in (("dense", sv.SV_FUSE_DENSE), ("fused", sv.SV_FUSE), ("pergate", 0)):
+                st.reset(0)
+                st.synchronize()
+                t0 = time.perf_counter()
+                st.run(g, flags)
+                st.synchronize()
+                el = time.perf_counter() - t0
+                st.run(inv, flags)
+                nrm = st.norm()
+                amp0 = complex(st.tensor[0].item())
+                off = float(st.tensor[torch.as_tensor(idx, device=st.tensor.device)].abs().max().item())
+                res[name] = {"ms": round(el * 1e3, 1), "gates_per_s": round(len(g) / el, 1),
+                             "mirror_abs_err_at_0": abs(amp0 - 1.0), "mirror_max_abs_sampled": off,
+                             "norm_drift": abs(nrm - 1.0)}
+                log(f"[bench] xl {tag} {name}: {el * 1e3:.0f} ms, |psi0-1| {abs(amp0 - 1.0):.2e}")
+        finally:
+            st.close()
+            torch.cuda.empty_cache()
+        out[tag] = res
+    return out
+
+
 def run_serving(arrivals, rate=100.0, seed=0):
     from paper_1801_01037_amd import serving
     reqs = serving.poisson_requests(rate, arrivals, seed)
@@ -306,6 +412,24 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
         del src, dst
+    if args.mode in ("sweep", "xl"):
+        extra = run_sweep(sv, torch, args.qubits, args.reps) if args.mode == "sweep" else run_xl(sv, torch)
+        if args.mode == "sweep":
+            value = extra["c128"]["one_qubit_gates_per_s"]
+            workload = (f"{args.qubits}-qubit per-gate timings: Haar 2x2 on every qubit, CNOTs, "
+                        "controlled phases, general 5-qubit gates; median of "
+                        f"{args.reps} HIP-event timings each")
+        else:
+            value = extra["c128_33q"]["dense"]["gates_per_s"]
+            workload = ("33-qubit complex128 / 34-qubit complex64 seeded depth-10 layered circuit, "
+                        "dense 5-qubit blocks vs tile passes vs gate by gate, with mirror error")
+        print(json.dumps({"metric": "30q gates/s and % HBM peak, c64 vs c128; batched p50/p99 circuit latency",
+                          "value": value, "unit": "gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": workload, "mode": args.mode},
+                          args.mode: extra}))
+        return
     flags = {"fused": sv.SV_FUSE, "pergate": 0, "dense": sv.SV_FUSE_DENSE}[args.mode]
     n = args.qubits
     log(f"[bench] c128 n={n} mode={args.mode} steps={args.steps} warmup={args.warmup}")
