@@ -62,6 +62,9 @@ def parse():
                     help="arrivals of each serving sample (0: no serving sample)")
     ap.add_argument("--serving-rates", default="100,1000",
                     help="offered request rates (per second) of the serving samples")
+    ap.add_argument("--serving-seconds", type=float, default=0.0,
+                    help="if > 0, each serving sample has rate x this many arrivals (at "
+                         "least 16, at most --serving-arrivals)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a plain copy kernel of "
                          "known size, for scaling memory-traffic counters)")
@@ -453,8 +456,11 @@ def main():
     if args.serving_arrivals:
         serving_stats = []
         for rate in [float(r) for r in args.serving_rates.split(",") if r]:
-            log(f"[bench] serving: {args.serving_arrivals} arrivals at {rate:g}/s")
-            serving_stats.append(run_serving(args.serving_arrivals, rate))
+            arrivals = args.serving_arrivals
+            if args.serving_seconds > 0:
+                arrivals = min(arrivals, max(16, int(rate * args.serving_seconds)))
+            log(f"[bench] serving: {arrivals} arrivals at {rate:g}/s")
+            serving_stats.append(run_serving(arrivals, rate))
             log(f"[bench] serving p50 {serving_stats[-1].get('p50_ms')} ms "
                 f"p99 {serving_stats[-1].get('p99_ms')} ms")
     cpu = None
