@@ -1373,12 +1373,6 @@ int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool 
 // ---- planned circuits and batched launches -----------------------------------
 
 namespace svk {
-namespace {
-
-}  // namespace
-}  // namespace svk
-
-namespace svk {
 
 int wall_clock_khz()
 {
