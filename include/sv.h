@@ -254,12 +254,13 @@ sv_status sv_batch_destroy(sv_batch b);
 sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task);
 /* Persistent launch for small circuits: a circuit whose passes have at most
  * max_tiles tiles (2^(n-12) for n > 12, one below) runs whole, every pass in
- * order, on the one work-group that takes it from a queue counter; one launch
- * covers all of them, ahead of the levels of the larger circuits. No
+ * order, on one work-group (work-group w takes circuits w, w + G, ..., least
+ * work first); one launch covers all of them and runs on a second stream of
+ * the batch, beside the levels of the larger circuits (forked from and joined
+ * back into the batch stream; captured with them under SV_GRAPH). No
  * work-group ever waits for another (between passes a work-group only fences
- * its own stores and meets its own waves), so the launch ends once the queue
- * is empty. Results are bit for bit those of the level launches. max_tiles =
- * 0 (the default) turns it off; at most 2^20. */
+ * its own stores and meets its own waves). Results are bit for bit those of the
+ * level launches. max_tiles = 0 (the default) turns it off; at most 2^20. */
 sv_status sv_batch_persist(sv_batch b, int32_t max_tiles);
 /* Queues passes [first_pass[i], first_pass[i] + pass_count[i]) of plans[i],
  * i < count, on the batch's stream (first_pass NULL: from 0; pass_count NULL:

@@ -1415,6 +1415,8 @@ struct sv_batch_s {
     sv_dtype dt = SV_C64;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;     // private stream for graph capture
+    hipStream_t side = nullptr;        // the persistent launch runs here, beside the levels
+    hipEvent_t fork = nullptr, join = nullptr;
     int blocks_per_cu = 2;
     uint32_t tiles_per_task = 8;
     int32_t persist_tiles = 0;         // circuits of at most this many tiles per pass
@@ -1561,6 +1563,12 @@ sv_status sv_batch_destroy(sv_batch b)
     (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->side) {
+        (void)hipStreamSynchronize(b->side);
+        (void)hipStreamDestroy(b->side);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
     if (b->work.dev) (void)hipFree(b->work.dev);
     if (b->gimg.dev) (void)hipFree(b->gimg.dev);
     if (b->host) (void)hipHostFree(b->host);
@@ -1721,20 +1729,32 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     return SV_OK;
 }
 
-// Queues the persistent launch (if any circuit takes it) and one launch per
-// level of `img` on `st`.
+// Queues the persistent launch (if any circuit takes it) on the side stream,
+// forked from `st` after the upload and joined back at the end, and one launch
+// per level of `img` on `st`: the two work on disjoint states, so the short
+// circuits run beside the first levels of the long ones. Both streams have the
+// default priority; under capture the side stream joins the graph through the
+// fork event.
 sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
 {
     using namespace svk;
     char *d = static_cast<char *>(img.dev);
-    if (!img.pcirc.empty()) {
+    const bool side = !img.pcirc.empty();
+    if (side) {
+        if (!b->side || !b->fork || !b->join) return berr(SV_EDEVICE, "side stream not set up");
+        hipError_t e = hipEventRecord(b->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork, 0);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("side stream: ") + hipGetErrorString(e));
+    }
+    if (side) {
         PersistArgs p{};
         p.circs = reinterpret_cast<const PersistCircuit *>(d + img.off_circ);
         p.passes = reinterpret_cast<const TileArgs *>(d + img.off_pass);
         p.t_start = reinterpret_cast<uint64_t *>(d + img.off_pstart);
         p.t_end = reinterpret_cast<uint64_t *>(d + img.off_pend);
         p.count = uint32_t(img.pcirc.size());
-        hipError_t e = launch_persist(p, b->dt == SV_C64, b->blocks_per_cu, st);
+        hipError_t e = launch_persist(p, b->dt == SV_C64, b->blocks_per_cu, b->side);
+        if (e == hipSuccess) e = hipEventRecord(b->join, b->side);
         if (e != hipSuccess) return berr(SV_EDEVICE, std::string("persistent launch: ") + hipGetErrorString(e));
     }
     BatchArgs a{};
@@ -1747,6 +1767,10 @@ sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
         a.task_end = img.level0[lev + 1];
         hipError_t e = launch_level(a, b->dt == SV_C64, b->blocks_per_cu, st);
         if (e != hipSuccess) return berr(SV_EDEVICE, std::string("level launch: ") + hipGetErrorString(e));
+    }
+    if (side) {
+        hipError_t e = hipStreamWaitEvent(st, b->join, 0);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("side join: ") + hipGetErrorString(e));
     }
     return SV_OK;
 }
@@ -1780,6 +1804,13 @@ sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pa
         key.push_back(reinterpret_cast<uintptr_t>(p));
         key.push_back(uintptr_t(first[i]));
         key.push_back(uintptr_t(cnt[i]));
+    }
+    if (b->persist_tiles > 0) {   // the side stream and its events exist before any capture
+        hipError_t e = hipSuccess;
+        if (!b->side) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess && !b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess && !b->join) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("side stream: ") + hipGetErrorString(e));
     }
     if (!(flags & SV_GRAPH)) {
         if (sv_status st = prepare_batch(b, b->work, plans, first, cnt, b->stream)) return st;
