@@ -7,8 +7,11 @@
 // c set (caption of Algorithm 1), several controls (a Toffoli gate has two) to
 // indices with all of them set. Instead of the paper's two nested loops, a
 // flat work index is expanded by inserting the fixed bits (target = 0,
-// controls = 1), so consecutive lanes touch consecutive 16-byte chunks of both
-// halves of every pair and both streams are coalesced for any t.
+// controls = 1) that select whole 128-byte lines, so consecutive lanes touch
+// consecutive 16-byte chunks and every line is read and written whole: when
+// the two halves of a pair lie in different lines they form two coalesced
+// streams; when they lie in one line, lanes holding the two chunks swap them
+// by a cross-lane permute; controls inside a line are tested per amplitude.
 #include <type_traits>
 
 #include "sv_internal.h"
@@ -48,25 +51,71 @@ __device__ __forceinline__ void pair_update(R &ar, R &ai, R &br, R &bi, const CM
     ar = nar; ai = nai; br = nbr; bi = nbi;
 }
 
-// Where the two amplitudes of a pair sit relative to 16-byte chunks.
+// Where the two amplitudes of a pair sit relative to 16-byte chunks and
+// 128-byte lines (8 chunks).
 enum Layout {
-    kSplit = 0,     // a and b in different chunks, 2^t apart; every amp of a chunk pairs
-    kInChunk = 1,   // c64, t = 0: one chunk holds (a, b)
-    kSplitOdd = 2,  // c64, control 0: split chunks, only the odd amplitude is controlled on
+    kSplit = 0,    // a and b in different lines, 2^t apart: two coalesced streams
+    kLane = 1,     // a and b in different chunks of one line: lanes exchange chunks
+    kInChunk = 2,  // complex64, t = 0: one chunk holds (a, b)
 };
 
 template <typename R>
 struct PairArgs {
     void *psi;
-    uint64_t items;       // work items (chunk pairs, or chunks for kInChunk)
+    uint64_t items;       // work items: chunk pairs (kSplit) or chunks
     uint64_t tstride;     // 2^t in amplitudes
+    uint64_t clow;        // controls below the line: tested per amplitude
     int nins;             // fixed index bits to insert, ascending positions
     uint64_t vals;        // bit k: the value inserted at pos[k]
     CMat<R> m;
     uint8_t pos[64];
 };
 
-template <bool C64, int LAYOUT, bool SWAP, int U>
+// Chunk index of work item `item`: the fixed bits (all at or above the line)
+// inserted into item * E, over E.
+template <uint64_t E, typename A>
+__device__ __forceinline__ uint64_t chunk_of(uint64_t item, const A &a)
+{
+    uint64_t x = item * E;
+    for (int k = 0; k < a.nins; ++k) x = insert_bit(x, a.pos[k], (a.vals >> k) & 1u);
+    return x / E;
+}
+
+// (a, b) of one pair, updated when its index i has every low control set.
+template <typename R, bool SWAP>
+__device__ __forceinline__ void pair_if(R &ar, R &ai, R &br, R &bi, uint64_t i,
+                                        const PairArgs<R> &a)
+{
+    if ((i & a.clow) != a.clow) return;
+    if constexpr (SWAP) {
+        R t = ar; ar = br; br = t;
+        t = ai; ai = bi; bi = t;
+    } else {
+        pair_update<R>(ar, ai, br, bi, a.m);
+    }
+}
+
+// One output of a pair whose halves sit in two lanes: this lane holds `own`
+// (the half with bit t = hi) and receives the other half `oth`.
+template <typename R, bool SWAP>
+__device__ __forceinline__ void half_if(R &r, R &i, R orr, R oi, bool hi, uint64_t idx,
+                                        const PairArgs<R> &a)
+{
+    if ((idx & a.clow) != a.clow) return;
+    if constexpr (SWAP) {
+        r = orr; i = oi;
+    } else if (!hi) {
+        const R nr = a.m.r11 * r - a.m.i11 * i + a.m.r12 * orr - a.m.i12 * oi;
+        const R ni = a.m.r11 * i + a.m.i11 * r + a.m.r12 * oi + a.m.i12 * orr;
+        r = nr; i = ni;
+    } else {
+        const R nr = a.m.r21 * orr - a.m.i21 * oi + a.m.r22 * r - a.m.i22 * i;
+        const R ni = a.m.r21 * oi + a.m.i21 * orr + a.m.r22 * i + a.m.i22 * r;
+        r = nr; i = ni;
+    }
+}
+
+template <bool C64, int LAYOUT, bool SWAP, bool NT, int U>
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs<std::conditional_t<C64, float, double>> a)
 {
     using R = std::conditional_t<C64, float, double>;
@@ -75,56 +124,66 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs<std::conditional_t<C64
     V *p = static_cast<V *>(a.psi);
     const uint64_t first = uint64_t(blockIdx.x) * (kBlock * U) + threadIdx.x;
 
-    V va[U], vb[U];
-    uint64_t ca[U], cb[U];
+    if constexpr (LAYOUT == kLane) {
+        // Consecutive lanes hold consecutive chunks of whole lines, so the
+        // partner chunk (2^t / E chunks away, within the line) is in lane
+        // lane ^ (2^t / E) of the same wave. Every lane takes part in the
+        // exchange; lanes past the end carry zeros and store nothing.
+        const int d = int(a.tstride / E);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint64_t item = first + uint64_t(u) * kBlock;
-        uint64_t x = item * E;
-        for (int k = 0; k < a.nins; ++k) x = insert_bit(x, a.pos[k], (a.vals >> k) & 1u);
-        ca[u] = x / E;
-        cb[u] = (x + a.tstride) / E;
-        if (item < a.items) {
-            va[u] = p[ca[u]];
-            if (LAYOUT != kInChunk) vb[u] = p[cb[u]];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint64_t item = first + uint64_t(u) * kBlock;
-        if (item >= a.items) continue;
-        if constexpr (C64) {
-            if constexpr (LAYOUT == kSplit) {
-                if constexpr (SWAP) {
-                    V t = va[u]; va[u] = vb[u]; vb[u] = t;
-                } else {
-                    pair_update<R>(va[u].x, va[u].y, vb[u].x, vb[u].y, a.m);
-                    pair_update<R>(va[u].z, va[u].w, vb[u].z, vb[u].w, a.m);
-                }
-            } else if constexpr (LAYOUT == kInChunk) {
-                if constexpr (SWAP) {
-                    va[u] = make_float4(va[u].z, va[u].w, va[u].x, va[u].y);
-                } else {
-                    pair_update<R>(va[u].x, va[u].y, va[u].z, va[u].w, a.m);
-                }
-            } else {  // kSplitOdd
-                if constexpr (SWAP) {
-                    R z = va[u].z, w = va[u].w;
-                    va[u].z = vb[u].z; va[u].w = vb[u].w;
-                    vb[u].z = z; vb[u].w = w;
-                } else {
-                    pair_update<R>(va[u].z, va[u].w, vb[u].z, vb[u].w, a.m);
-                }
+        for (int u = 0; u < U; ++u) {
+            const uint64_t item = first + uint64_t(u) * kBlock;
+            const bool live = item < a.items;
+            const uint64_t c = chunk_of<E>(item, a);
+            V v;
+            if (live) v = ld16<NT>(&p[c]);
+            else if constexpr (C64) v = make_float4(0.f, 0.f, 0.f, 0.f);
+            else v = make_double2(0.0, 0.0);
+            V o;
+            o.x = __shfl_xor(v.x, d);
+            o.y = __shfl_xor(v.y, d);
+            if constexpr (C64) {
+                o.z = __shfl_xor(v.z, d);
+                o.w = __shfl_xor(v.w, d);
             }
-        } else {
-            if constexpr (SWAP) {
-                V t = va[u]; va[u] = vb[u]; vb[u] = t;
+            const bool hi = (c & uint64_t(d)) != 0;
+            if constexpr (C64) {
+                half_if<R, SWAP>(v.x, v.y, o.x, o.y, hi, c * E, a);
+                half_if<R, SWAP>(v.z, v.w, o.z, o.w, hi, c * E + 1, a);
             } else {
-                pair_update<R>(va[u].x, va[u].y, vb[u].x, vb[u].y, a.m);
+                half_if<R, SWAP>(v.x, v.y, o.x, o.y, hi, c, a);
+            }
+            if (live) st16<NT>(&p[c], v);
+        }
+        return;
+    } else {
+        V va[U], vb[U];
+        uint64_t ca[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t item = first + uint64_t(u) * kBlock;
+            ca[u] = chunk_of<E>(item, a);
+            if (item < a.items) {
+                va[u] = ld16<NT>(&p[ca[u]]);
+                if (LAYOUT == kSplit) vb[u] = ld16<NT>(&p[ca[u] + a.tstride / E]);
             }
         }
-        p[ca[u]] = va[u];
-        if (LAYOUT != kInChunk) p[cb[u]] = vb[u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t item = first + uint64_t(u) * kBlock;
+            if (item >= a.items) continue;
+            const uint64_t i0 = ca[u] * E;
+            if constexpr (LAYOUT == kInChunk) {
+                pair_if<R, SWAP>(va[u].x, va[u].y, va[u].z, va[u].w, i0, a);
+            } else if constexpr (C64) {
+                pair_if<R, SWAP>(va[u].x, va[u].y, vb[u].x, vb[u].y, i0, a);
+                pair_if<R, SWAP>(va[u].z, va[u].w, vb[u].z, vb[u].w, i0 + 1, a);
+            } else {
+                pair_if<R, SWAP>(va[u].x, va[u].y, vb[u].x, vb[u].y, i0, a);
+            }
+            st16<NT>(&p[ca[u]], va[u]);
+            if (LAYOUT == kSplit) st16<NT>(&p[ca[u] + a.tstride / E], vb[u]);
+        }
     }
 }
 
@@ -159,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs<C64> a)
 struct DiagArgs {
     void *psi;
     uint64_t items;       // chunks to visit
-    int nins;             // bits fixed to 1 in every visited index (ascending)
+    int nins;             // bits at or above the line fixed to 1 in every visited index (ascending)
     int pos[4];
     int count;
     DiagTerm t[kMaxDiagTerms];
@@ -180,7 +239,9 @@ __device__ __forceinline__ uint64_t turn_of(uint64_t i, const DiagArgs &a)
     return T;
 }
 
-template <bool C64, int U>
+// Chunks whose phase is 1 are written back only when streaming (NT), so
+// that every line goes out whole.
+template <bool C64, bool NT, int U>
 __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a)
 {
     using V = std::conditional_t<C64, float4, double2>;
@@ -195,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a)
         uint64_t x = item * E;
         for (int k = 0; k < a.nins; ++k) x = insert_bit(x, a.pos[k], 1);
         ci[u] = x / E;
-        if (item < a.items) v[u] = p[ci[u]];
+        if (item < a.items) v[u] = ld16<NT>(&p[ci[u]]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -204,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a)
         const uint64_t i0 = ci[u] * E;
         if constexpr (C64) {
             const uint64_t T0 = turn_of(i0, a), T1 = turn_of(i0 + 1, a);
-            if ((T0 | T1) == 0) continue;
+            if (!NT && (T0 | T1) == 0) continue;
             double c, s;
             if (T0) {
                 turn_phase(T0, c, s);
@@ -222,18 +283,19 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a)
             }
         } else {
             const uint64_t T = turn_of(i0, a);
-            if (T == 0) continue;
-            double c, s;
-            turn_phase(T, c, s);
-            const double re = v[u].x * c - v[u].y * s;
-            const double im = v[u].x * s + v[u].y * c;
-            v[u].x = re; v[u].y = im;
+            if (!NT && T == 0) continue;
+            if (T) {
+                double c, s;
+                turn_phase(T, c, s);
+                const double re = v[u].x * c - v[u].y * s;
+                const double im = v[u].x * s + v[u].y * c;
+                v[u].x = re; v[u].y = im;
+            }
         }
-        p[ci[u]] = v[u];
+        st16<NT>(&p[ci[u]], v[u]);
     }
 }
 
-constexpr int kPairU = 4;
 constexpr int kDiagU = 2;
 
 inline unsigned grid_for(uint64_t items, int per_block)
@@ -241,14 +303,33 @@ inline unsigned grid_for(uint64_t items, int per_block)
     return unsigned((items + per_block - 1) / per_block);
 }
 
-template <bool C64, int LAYOUT, bool SWAP>
-hipError_t launch_pair_t(const PairArgs<std::conditional_t<C64, float, double>> &a,
+// Pairs 16 MiB or more apart run four chunk pairs per thread, nearer pairs
+// one: the faster of the two at each distance on gfx950.
+constexpr uint64_t kWideStrideBytes = uint64_t(16) << 20;
+
+template <bool C64, int LAYOUT, bool SWAP, bool NT>
+hipError_t launch_pair_u(const PairArgs<std::conditional_t<C64, float, double>> &a, bool wide,
                          hipStream_t st)
 {
-    if (a.items == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pair<C64, LAYOUT, SWAP, kPairU>), dim3(grid_for(a.items, kBlock * kPairU)),
-                       dim3(kBlock), 0, st, a);
+    if (LAYOUT == kSplit && wide)
+        hipLaunchKernelGGL((k_pair<C64, LAYOUT, SWAP, NT, 4>), dim3(grid_for(a.items, kBlock * 4)),
+                           dim3(kBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair<C64, LAYOUT, SWAP, NT, 1>), dim3(grid_for(a.items, kBlock)),
+                           dim3(kBlock), 0, st, a);
     return hipGetLastError();
+}
+
+template <bool C64, int LAYOUT>
+hipError_t launch_pair_t(const PairArgs<std::conditional_t<C64, float, double>> &a, bool swap,
+                         bool nt, bool wide, hipStream_t st)
+{
+    if (a.items == 0) return hipSuccess;
+    if (swap)
+        return nt ? launch_pair_u<C64, LAYOUT, true, true>(a, wide, st)
+                  : launch_pair_u<C64, LAYOUT, true, false>(a, wide, st);
+    return nt ? launch_pair_u<C64, LAYOUT, false, true>(a, wide, st)
+              : launch_pair_u<C64, LAYOUT, false, false>(a, wide, st);
 }
 
 template <bool C64>
@@ -257,22 +338,19 @@ hipError_t launch_pair_p(void *psi, int n, int t, uint64_t cmask, const Mat2 &m,
 {
     using R = std::conditional_t<C64, float, double>;
     constexpr int lgE = C64 ? 1 : 0;
+    constexpr int kLineBit = lgE + 3;                    // amplitude bits inside a 128-byte line
+    const uint64_t line_mask = (uint64_t(1) << kLineBit) - 1;
     PairArgs<R> a{};
     a.psi = psi;
     a.tstride = uint64_t(1) << t;
     a.m = to_cmat<R>(m);
-    // Fixed bits inserted into the work index, ascending: the target bit (0)
-    // when the pair spans two chunks, every control bit (1) that is constant
-    // over a chunk. A complex64 control on bit 0 selects the odd amplitude of
-    // each chunk instead (kSplitOdd).
-    int layout;
-    if (t >= lgE) {
-        layout = (lgE > 0 && (cmask & 1u)) ? kSplitOdd : kSplit;
-    } else {
-        layout = kInChunk;
-    }
-    const uint64_t ins_mask = (layout != kInChunk ? (uint64_t(1) << t) : 0) |
-                              (cmask & ~((uint64_t(1) << lgE) - 1));
+    // Controls inside a line are tested per amplitude, so every line the
+    // launch touches is read and written whole; controls above it are
+    // inserted into the work index as fixed 1 bits, and so is the target
+    // (as 0) when the pair spans two lines.
+    a.clow = cmask & line_mask;
+    const int layout = t >= kLineBit ? kSplit : (t >= lgE ? kLane : kInChunk);
+    const uint64_t ins_mask = (layout == kSplit ? a.tstride : 0) | (cmask & ~line_mask);
     int nins = 0;
     for (int b = 0; b < 64; ++b) {
         if (!((ins_mask >> b) & 1)) continue;
@@ -282,14 +360,12 @@ hipError_t launch_pair_p(void *psi, int n, int t, uint64_t cmask, const Mat2 &m,
     }
     a.nins = nins;
     a.items = (uint64_t(1) << n) >> (lgE + nins);
-    if (layout == kSplit)
-        return swap_only ? launch_pair_t<C64, kSplit, true>(a, st)
-                         : launch_pair_t<C64, kSplit, false>(a, st);
-    if (layout == kInChunk)
-        return swap_only ? launch_pair_t<C64, kInChunk, true>(a, st)
-                         : launch_pair_t<C64, kInChunk, false>(a, st);
-    return swap_only ? launch_pair_t<C64, kSplitOdd, true>(a, st)
-                     : launch_pair_t<C64, kSplitOdd, false>(a, st);
+    const bool nt = (uint64_t(1) << n) * (C64 ? 8 : 16) > kStreamBytes;
+    const bool wide = a.tstride * (C64 ? 8 : 16) >= kWideStrideBytes;
+    if (layout == kSplit) return launch_pair_t<C64, kSplit>(a, swap_only, nt, wide, st);
+    if (layout == kLane) return launch_pair_t<C64, kLane>(a, swap_only, nt, wide, st);
+    if constexpr (C64) return launch_pair_t<C64, kInChunk>(a, swap_only, nt, wide, st);
+    return hipErrorInvalidValue;   // complex128 pairs always span two chunks
 }
 
 }  // namespace
@@ -329,15 +405,21 @@ hipError_t launch_diag(void *psi, int n, sv_dtype dt, const DiagTerm *terms, int
         a.t[k] = terms[k];
         common &= terms[k].mask & terms[k].val;   // bits every term needs set
     }
+    // Only bits that select whole 128-byte lines are inserted: lines are read
+    // whole, and bits inside a line are left to the per-amplitude terms.
     a.nins = 0;
-    for (int b = lgE; b < n && a.nins < 4; ++b)
+    for (int b = lgE + 3; b < n && a.nins < 4; ++b)
         if ((common >> b) & 1) a.pos[a.nins++] = b;
     a.items = (uint64_t(1) << n) >> (lgE + a.nins);
     const unsigned grid = grid_for(a.items, kBlock * kDiagU);
-    if (dt == SV_C64)
-        hipLaunchKernelGGL((k_diag<true, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_diag<false, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+    const bool nt = (uint64_t(1) << n) * uint64_t(elem_bytes(dt)) > kStreamBytes;
+    if (dt == SV_C64) {
+        if (nt) hipLaunchKernelGGL((k_diag<true, true, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_diag<true, false, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+    } else {
+        if (nt) hipLaunchKernelGGL((k_diag<false, true, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_diag<false, false, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ __device__ __forceinline__ double block_sum(double v)
     return s;
 }
 
-template <bool C64>
+template <bool C64, bool NT>
 __global__ __launch_bounds__(kBlock) void k_norm_partial(const void *psi, uint64_t chunks,
                                                          double *partials)
 {
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_partial(const void *psi, uint64
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     double acc = 0.0;
     for (uint64_t c = uint64_t(blockIdx.x) * kBlock + threadIdx.x; c < chunks; c += stride) {
-        const V v = p[c];
+        const V v = ld16<NT>(&p[c]);
         if constexpr (C64) {
             const double a = v.x, b = v.y, d = v.z, e = v.w;
             acc += (a * a + b * b) + (d * d + e * e);
@@ -85,12 +85,15 @@ hipError_t launch_norm(const void *psi, int n, sv_dtype dt, double *partials, do
                        hipStream_t st)
 {
     const uint64_t chunks = (uint64_t(1) << n) >> chunk_log2(dt);
-    if (dt == SV_C64)
-        hipLaunchKernelGGL(k_norm_partial<true>, dim3(kNormBlocks), dim3(kBlock), 0, st, psi,
-                           chunks, partials);
-    else
-        hipLaunchKernelGGL(k_norm_partial<false>, dim3(kNormBlocks), dim3(kBlock), 0, st, psi,
-                           chunks, partials);
+    const bool nt = (uint64_t(1) << n) * uint64_t(elem_bytes(dt)) > kStreamBytes;
+    const dim3 grid(kNormBlocks), block(kBlock);
+    if (dt == SV_C64) {
+        if (nt) hipLaunchKernelGGL((k_norm_partial<true, true>), grid, block, 0, st, psi, chunks, partials);
+        else hipLaunchKernelGGL((k_norm_partial<true, false>), grid, block, 0, st, psi, chunks, partials);
+    } else {
+        if (nt) hipLaunchKernelGGL((k_norm_partial<false, true>), grid, block, 0, st, psi, chunks, partials);
+        else hipLaunchKernelGGL((k_norm_partial<false, false>), grid, block, 0, st, psi, chunks, partials);
+    }
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormBlocks), 0, st, partials, out_dev);
     return hipGetLastError();
 }

@@ -32,6 +32,46 @@ struct DiagTerm {
 };
 constexpr int kMaxDiagTerms = 64;
 
+// ---- streaming 16-byte access -----------------------------------------------
+// A load or store of one 16-byte chunk, with the nontemporal hint when NT: for
+// state passes that touch every line once and are far larger than the caches,
+// so the lines stream through instead of displacing others. A launch whose
+// lanes read only part of a 128-byte line per access leaves the rest of the
+// line to a later access, which the hint would send back to HBM; such
+// launches take NT = false.
+// States larger than the last-level cache (256 MiB) take the hint: a pass over
+// them touches every line once, and the next pass cannot find them in cache.
+constexpr uint64_t kStreamBytes = uint64_t(256) << 20;
+
+template <typename V> struct Native16;
+template <> struct Native16<float4> { typedef float T __attribute__((ext_vector_type(4))); };
+template <> struct Native16<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld16(const V *p)
+{
+    if constexpr (NT) {
+        using N = typename Native16<V>::T;
+        const N n = __builtin_nontemporal_load(reinterpret_cast<const N *>(p));
+        V v;
+        *reinterpret_cast<N *>(&v) = n;
+        return v;
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void st16(V *p, const V &v)
+{
+    if constexpr (NT) {
+        using N = typename Native16<V>::T;
+        __builtin_nontemporal_store(*reinterpret_cast<const N *>(&v), reinterpret_cast<N *>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // ---- launchers (kernels_gate.hip) ----------------------------------------
 // All take the state pointer, qubit count and stream; they validate nothing.
 hipError_t launch_init(void *psi, int n, sv_dtype dt, uint64_t basis, hipStream_t st);

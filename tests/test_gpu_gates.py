@@ -197,3 +197,41 @@ def test_torch_wrapped_state_matches_owned_state():
         a = st.tensor.cpu().numpy()
     ref = oracle.simulate(n, g)
     assert np.max(np.abs(a - ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype,n", [(sv.SV_C128, 25), (sv.SV_C64, 26)], ids=["c128-25", "c64-26"])
+def test_streamed_state_every_pair_layout(dtype, n):
+    """A state past the last-level cache (512 MiB) takes the streaming
+    accesses; targets inside a 128-byte line take the lane exchange, targets
+    16 MiB or more apart four pairs per thread, and controls inside a line are
+    tested per amplitude, as are phases on bits inside a line. One sequence
+    covers each, against the oracle."""
+    def phase(theta):
+        return (1.0, 0.0, 0.0, 0.0, 0.0, 0.0, math.cos(theta), math.sin(theta))
+
+    psi0 = rounded(qc.random_state(n, 2500 + n), dtype)
+    mats = qc.haar_su2(2600 + n, 16)
+    seq = [((), 0, mats[0]), ((), 1, mats[1]), ((), 2, mats[2]), ((), 3, mats[3]),
+           ((), 4, mats[4]), ((), n - 4, mats[5]), ((), n - 1, mats[6]),
+           ((0,), n - 1, qc.X_MATRIX), ((n - 1,), 0, mats[7]), ((2,), 1, mats[8]),
+           ((0,), 3, mats[9]), ((1, n - 2), 3, mats[10]), ((0, 1, 2), n - 1, qc.X_MATRIX),
+           ((3, 20), 0, qc.X_MATRIX), ((0, 5), 2, mats[11]),
+           ((0,), n - 1, phase(0.3)), ((14,), 15, phase(0.5)), ((2,), 5, phase(0.7)),
+           ((0, 1), 2, phase(1.1))]
+    h = state_from_host(n, dtype, psi0)
+    try:
+        for controls, t, m in seq:
+            if controls:
+                sv.sv_apply_mcu(h, controls, t, m)
+            else:
+                sv.sv_apply_1q(h, t, m)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+    ref = psi0.copy()
+    for controls, t, m in seq:
+        if controls:
+            oracle.apply_mcu(ref, controls, t, m)
+        else:
+            oracle.apply_1q(ref, t, m)
+    assert_close(got, ref, dtype, len(seq), f"n={n}")
