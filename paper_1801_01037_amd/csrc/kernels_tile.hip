@@ -456,10 +456,26 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A tile amplitude from or to HBM; NT: with the nontemporal hint, for states
+// larger than the last-level cache, whose lines a pass touches once.
+template <bool NT, typename A>
+__device__ __forceinline__ A ld_amp(const A *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, typename A>
+__device__ __forceinline__ void st_amp(A *p, const A &v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Processes tiles g = g0, g0 + gstep, ... below gend of the pass `a` with one
 // work-group. Threads tid >= 2^(L-K) (a tile smaller than the work-group) take
 // part in the barriers only.
-template <bool C64, int K>
+template <bool C64, int K, bool NT = false>
 __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
                                           uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab)
 {
@@ -506,7 +522,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
         if (active) {
             A pv[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) pv[r] = psi[gbase | dtv | roff[r]];
+            for (int r = 0; r < NR; ++r) pv[r] = ld_amp<NT>(&psi[gbase | dtv | roff[r]]);
 #pragma unroll
             for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tv + uint32_t(r) * W)] = pv[r];
         }
@@ -572,10 +588,10 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                 for (int j = 0; j < a.L - K; ++j)
                     pt |= ((ts >> j) & 1u) << uint32_t((osrc >> (4 * j)) & 15u);
 #pragma unroll
-                for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(pt | proff[r])];
+                for (int r = 0; r < NR; ++r) st_amp<NT>(&psi[gb | roff[r]], lds[lds_slot<C64>(pt | proff[r])]);
             } else {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) psi[gb | roff[r]] = lds[lds_slot<C64>(ts + uint32_t(r) * W)];
+                for (int r = 0; r < NR; ++r) st_amp<NT>(&psi[gb | roff[r]], lds[lds_slot<C64>(ts + uint32_t(r) * W)]);
             }
         }
         if (permute) lds_barrier();
@@ -590,14 +606,14 @@ __device__ __forceinline__ AmpT<C64> *lds_base()
 }
 
 // One pass: work-group blockIdx.x walks tiles blockIdx.x, +gridDim.x, ...
-template <bool C64, int K, int MAXT>
+template <bool C64, int K, int MAXT, bool NT = false>
 __global__ __launch_bounds__(MAXT) void k_tile(TileArgs a)
 {
     using A = AmpT<C64>;
     A *lds = lds_base<C64>();
     const uint32_t size = 1u << a.L;
     A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
-    run_tiles<C64, K>(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab);
+    run_tiles<C64, K, NT>(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab);
 }
 
 // One pass level of a batch: every task (a chunk of tiles of one pass of one
@@ -718,7 +734,11 @@ hipError_t launch_dt(const TileArgs &a, int K, size_t lds, hipStream_t st)
     case 1: return launch_k(k_tile<C64, 1, 1024>, C64, a, K, lds, st);
     case 2: return launch_k(k_tile<C64, 2, 1024>, C64, a, K, lds, st);
     case 3: return launch_k(k_tile<C64, 3, C64 ? 1024 : 512>, C64, a, K, lds, st);
-    case 4: return launch_k(k_tile<C64, 4, C64 ? 512 : 256>, C64, a, K, lds, st);
+    case 4:
+        // Only states past the last-level cache stream; they all run K = 4.
+        if ((a.ntiles << a.L) * uint64_t(C64 ? 8 : 16) > kStreamBytes)
+            return launch_k(k_tile<C64, 4, C64 ? 512 : 256, true>, C64, a, K, lds, st);
+        return launch_k(k_tile<C64, 4, C64 ? 512 : 256>, C64, a, K, lds, st);
     }
     return hipErrorInvalidValue;
 }
