@@ -178,6 +178,22 @@ sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
  * All gates are validated before any work is queued. */
 sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags);
 
+/* Runs count independent circuits, circuits[c] (lens[c] gates) on states[c],
+ * with their work overlapping on the device: the circuit of section Quantum
+ * Circuits applied to many registers at once. Each result equals
+ * sv_run_circuit(states[c], circuits[c], lens[c], SV_FUSE) bit for bit.
+ * States must be distinct and may mix dtypes, sizes and streams. Circuits on
+ * n >= 4 qubits without several-control gates go into one batch per dtype
+ * (see sv_batch_run: default launch configuration), queued on the stream of
+ * that dtype's first such state after the earlier work of every member's
+ * stream; the others run alone with SV_FUSE. flags: 0, SV_FUSE (the same) and
+ * optionally SV_GRAPH (each batch captured and replayed). Synchronous: returns
+ * once every circuit has run. Every state, gate array and gate is validated
+ * before any work is queued, so SV_EINVAL leaves all states untouched. For
+ * repeated batches, plan once with sv_plan_create and run sv_batch_run. */
+sv_status sv_run_batch(sv_state *states, const sv_gate *const *circuits, const size_t *lens,
+                       size_t count, uint32_t flags);
+
 /* p_i = |alpha_i|^2 for i in [first, first + count), written to host memory
  * out_host (count doubles). Synchronous: waits for the stream. The squares are
  * formed in FP64 for both dtypes. */

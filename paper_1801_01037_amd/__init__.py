@@ -20,7 +20,7 @@ __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
     "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
-    "sv_run_circuit", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
+    "sv_run_circuit", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
     "sv_plan_passes", "sv_run_plan", "sv_batch_create", "sv_batch_destroy", "sv_batch_config",
@@ -80,6 +80,7 @@ _SIGNATURES = {
     "sv_sample_device": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
     "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
+    "sv_run_batch": ([_vp, _vp, _vp, _sz, _u32], _int),
     "sv_probs": ([_vp, _u64, _u64, _dp], _int),
     "sv_probs_device": ([_vp, _u64, _u64, _vp], _int),
     "sv_norm": ([_vp, _dp], _int),
@@ -227,6 +228,21 @@ def sv_run_circuit(h: int, gates: np.ndarray, flags: int = 0) -> None:
     if g.dtype != GATE_DTYPE:
         g = g.astype(GATE_DTYPE)
     _check(lib().sv_run_circuit(h, g.ctypes.data if len(g) else None, len(g), flags))
+
+
+def sv_run_batch(handles, circuits, flags: int = 0) -> None:
+    """Runs circuits[c] on handles[c] for every c as one batch (synchronous)."""
+    if len(handles) != len(circuits):
+        raise ValueError("one circuit per state")
+    arrs = []
+    for gates in circuits:
+        g = np.ascontiguousarray(gates)
+        arrs.append(g if g.dtype == GATE_DTYPE else g.astype(GATE_DTYPE))
+    k = len(arrs)
+    hs = (ctypes.c_void_p * max(k, 1))(*handles)
+    ps = (ctypes.c_void_p * max(k, 1))(*[g.ctypes.data if len(g) else None for g in arrs])
+    ls = (ctypes.c_size_t * max(k, 1))(*[len(g) for g in arrs])
+    _check(lib().sv_run_batch(hs, ps, ls, k, flags))
 
 
 def sv_probs(h: int, first: int, count: int) -> np.ndarray:

@@ -1,5 +1,6 @@
 // The C ABI declared in include/sv.h: argument checks, handle management and
 // dispatch of each request to the kernels. No exception leaves this file.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -424,6 +425,86 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = queue_gate(s, gates[i])) return st;
     return SV_OK;
+}
+
+sv_status sv_run_batch(sv_state *states, const sv_gate *const *circuits, const size_t *lens,
+                       size_t count, uint32_t flags)
+{
+    if (count == 0) return SV_OK;
+    if (!states || !circuits || !lens) return fail(SV_EINVAL, "null argument array");
+    if (flags & ~(SV_FUSE | SV_GRAPH)) return fail(SV_EINVAL, "unknown batch flags 0x%x", flags);
+    // Everything is checked before anything runs, so an invalid argument
+    // leaves every state untouched.
+    std::vector<sv_state> sorted(states, states + count);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(SV_EINVAL, "a state appears twice in the batch");
+    for (size_t c = 0; c < count; ++c) {
+        if (sv_status st = check_handle(states[c])) return st;
+        if (lens[c] && !circuits[c]) return fail(SV_EINVAL, "null gate array for circuit %zu", c);
+        for (size_t i = 0; i < lens[c]; ++i)
+            if (sv_status st = validate_gate(states[c], circuits[c][i], i)) return st;
+    }
+    // Circuits the planner takes (n >= 4, no several-control gates) go into one
+    // batch per dtype; the others run alone, planned, on their own streams.
+    std::vector<sv_plan> plans[2];
+    std::vector<sv_state> owners[2];
+    std::vector<size_t> alone;
+    auto destroy_plans = [&]() {
+        for (auto &v : plans)
+            for (sv_plan p : v) sv_plan_destroy(p);
+    };
+    for (size_t c = 0; c < count; ++c) {
+        const sv_gate *g = circuits[c];
+        const bool mcu = std::any_of(g, g + lens[c], [](const sv_gate &x) { return x.kind == SV_G_MCU; });
+        if (lens[c] == 0) continue;
+        if (states[c]->n < 4 || mcu) {
+            alone.push_back(c);
+            continue;
+        }
+        sv_plan p = nullptr;
+        if (sv_status st = sv_plan_create(states[c], g, lens[c], &p)) {
+            destroy_plans();
+            return st;
+        }
+        const int d = states[c]->dt == SV_C64 ? 0 : 1;
+        plans[d].push_back(p);
+        owners[d].push_back(states[c]);
+    }
+    sv_status result = SV_OK;
+    for (int d = 0; d < 2 && result == SV_OK; ++d) {
+        if (plans[d].empty()) continue;
+        sv_state lead = owners[d][0];
+        DeviceScope ds(lead->device);
+        // The batch runs on the first state's stream, after the earlier work
+        // queued on every state's own stream.
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            result = fail(SV_EDEVICE, "event creation failed");
+            break;
+        }
+        for (sv_state o : owners[d]) {
+            if (o->stream == lead->stream) continue;
+            (void)hipEventRecord(ev, o->stream);
+            (void)hipStreamWaitEvent(lead->stream, ev, 0);
+        }
+        sv_batch b = nullptr;
+        result = sv_batch_create(d == 0 ? SV_C64 : SV_C128, lead->stream, &b);
+        if (result == SV_OK)
+            result = sv_batch_run(b, plans[d].data(), nullptr, nullptr, plans[d].size(), flags & SV_GRAPH);
+        if (b) {
+            const sv_status sync = sv_batch_destroy(b);   // waits for the batch stream
+            if (result == SV_OK) result = sync;
+        }
+        (void)hipEventDestroy(ev);
+    }
+    for (size_t k = 0; k < alone.size() && result == SV_OK; ++k) {
+        const size_t c = alone[k];
+        result = sv_run_circuit(states[c], circuits[c], lens[c], SV_FUSE);
+        if (result == SV_OK) result = sv_synchronize(states[c]);
+    }
+    destroy_plans();
+    return result;
 }
 
 sv_status sv_probs_device(sv_state s, uint64_t first, uint64_t count, double *out_dev)

@@ -51,6 +51,13 @@ def test_rejects_bad_arguments_without_a_device(lib):
     assert lib.sv_destroy(None) == sv.SV_OK
     assert lib.sv_reset(None, 0) == sv.SV_EINVAL
     assert lib.sv_run_circuit(None, None, 1, 0) == sv.SV_EINVAL
+    assert lib.sv_run_batch(None, None, None, 1, 0) == sv.SV_EINVAL
+    assert lib.sv_run_batch(None, None, None, 0, 0) == sv.SV_OK
+    one = (ctypes.c_void_p * 1)(None)
+    lens = (ctypes.c_size_t * 1)(0)
+    assert lib.sv_run_batch(one, one, lens, 1, 0x100) == sv.SV_EINVAL
+    assert "flags" in sv.sv_last_error()
+    assert lib.sv_run_batch(one, one, lens, 1, sv.SV_FUSE) == sv.SV_EINVAL   # null state
     assert lib.sv_norm(None, None) == sv.SV_EINVAL
     assert lib.sv_synchronize(None) == sv.SV_EINVAL
     with pytest.raises(sv.SVError) as ei:

@@ -283,3 +283,65 @@ def test_persist_rejects_bad_values():
             assert e.value.status == sv.SV_EINVAL
     finally:
         sv.sv_batch_destroy(b)
+
+
+def test_run_batch_one_call_mixed_states():
+    """sv_run_batch: complex64 and complex128 states of several sizes and
+    streams, a circuit with a Toffoli and one on 3 qubits (both run alone), an
+    empty circuit; every result equals the circuit run alone with SV_FUSE."""
+    import torch
+    side = torch.cuda.Stream()
+    cases = [(12, sv.SV_C128, qc.layer_circuit(12, 6, 71), None),
+             (14, sv.SV_C64, qc.layer_circuit(14, 8, 72), side.cuda_stream),
+             (10, sv.SV_C64, np.concatenate([qc.layer_circuit(10, 3, 73),
+                                             qc.gate_mcu((0, 4), 9, qc.X_MATRIX),
+                                             qc.layer_circuit(10, 2, 74)]), None),
+             (3, sv.SV_C128, qc.layer_circuit(3, 5, 75), None),
+             (9, sv.SV_C128, qc.layer_circuit(9, 0, 76), None),
+             (16, sv.SV_C128, qc.qft_circuit(16), side.cuda_stream),
+             (11, sv.SV_C64, qc.qft_circuit(11), None)]
+    states = [sv.sv_create(n, dt, st) for n, dt, _, st in cases]
+    try:
+        for h, (n, _, _, _) in zip(states, cases):
+            sv.sv_reset(h, qc.random_basis_index(n, 700 + n))
+        sv.sv_run_batch(states, [g for _, _, g, _ in cases], sv.SV_FUSE)
+        outs = [sv.sv_copy_out(h) for h in states]
+    finally:
+        for h in states:
+            sv.sv_destroy(h)
+    for (n, dt, g, _), got in zip(cases, outs):
+        h = sv.sv_create(n, dt)
+        try:
+            sv.sv_reset(h, qc.random_basis_index(n, 700 + n))
+            sv.sv_run_circuit(h, g, sv.SV_FUSE)
+            want = sv.sv_copy_out(h)
+        finally:
+            sv.sv_destroy(h)
+        assert np.array_equal(got, want), (n, dt, len(g))
+        ref = oracle.basis_state(n, qc.random_basis_index(n, 700 + n))
+        oracle.run_circuit(ref, g)
+        assert_close(got, ref, dt, max(len(g), 1), f"n={n}")
+
+
+def test_run_batch_rejects_before_running():
+    """A repeated state or an invalid gate in any circuit is reported before
+    any work is queued: every state keeps its value."""
+    a = sv.sv_create(10, sv.SV_C128)
+    b = sv.sv_create(12, sv.SV_C128)
+    try:
+        sv.sv_reset(a, 5)
+        sv.sv_reset(b, 6)
+        good = qc.layer_circuit(10, 4, 81)
+        bad = qc.layer_circuit(12, 4, 82)
+        bad[3]["target"] = 12                      # outside the 12-qubit register
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_run_batch([a, b], [good, bad])
+        assert e.value.status == sv.SV_EINVAL
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_run_batch([a, a], [good, good])
+        assert e.value.status == sv.SV_EINVAL
+        assert np.array_equal(sv.sv_copy_out(a), oracle.basis_state(10, 5))
+        assert np.array_equal(sv.sv_copy_out(b), oracle.basis_state(12, 6))
+    finally:
+        sv.sv_destroy(a)
+        sv.sv_destroy(b)
