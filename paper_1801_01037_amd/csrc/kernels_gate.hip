@@ -298,6 +298,10 @@ __global__ __launch_bounds__(kBlock) void k_diag(DiagArgs a)
 
 constexpr int kDiagU = 2;
 
+// A launch holds fewer than 2^32 work-items along x; per-gate launches keep
+// to 2^31 and give each thread four items when a state has more.
+constexpr uint64_t kMaxLaunchItems = uint64_t(1) << 31;
+
 inline unsigned grid_for(uint64_t items, int per_block)
 {
     return unsigned((items + per_block - 1) / per_block);
@@ -311,7 +315,7 @@ template <bool C64, int LAYOUT, bool SWAP, bool NT>
 hipError_t launch_pair_u(const PairArgs<std::conditional_t<C64, float, double>> &a, bool wide,
                          hipStream_t st)
 {
-    if (LAYOUT == kSplit && wide)
+    if ((LAYOUT == kSplit && wide) || a.items > kMaxLaunchItems)
         hipLaunchKernelGGL((k_pair<C64, LAYOUT, SWAP, NT, 4>), dim3(grid_for(a.items, kBlock * 4)),
                            dim3(kBlock), 0, st, a);
     else
@@ -411,14 +415,20 @@ hipError_t launch_diag(void *psi, int n, sv_dtype dt, const DiagTerm *terms, int
     for (int b = lgE + 3; b < n && a.nins < 4; ++b)
         if ((common >> b) & 1) a.pos[a.nins++] = b;
     a.items = (uint64_t(1) << n) >> (lgE + a.nins);
-    const unsigned grid = grid_for(a.items, kBlock * kDiagU);
     const bool nt = (uint64_t(1) << n) * uint64_t(elem_bytes(dt)) > kStreamBytes;
+    if (a.items > kMaxLaunchItems * kDiagU) {     // up to 2^33 chunks: four per thread
+        const dim3 grid(grid_for(a.items, kBlock * 4));
+        if (dt == SV_C64) hipLaunchKernelGGL((k_diag<true, true, 4>), grid, dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_diag<false, true, 4>), grid, dim3(kBlock), 0, st, a);
+        return hipGetLastError();
+    }
+    const dim3 grid(grid_for(a.items, kBlock * kDiagU));
     if (dt == SV_C64) {
-        if (nt) hipLaunchKernelGGL((k_diag<true, true, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL((k_diag<true, false, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (nt) hipLaunchKernelGGL((k_diag<true, true, kDiagU>), grid, dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_diag<true, false, kDiagU>), grid, dim3(kBlock), 0, st, a);
     } else {
-        if (nt) hipLaunchKernelGGL((k_diag<false, true, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL((k_diag<false, false, kDiagU>), dim3(grid), dim3(kBlock), 0, st, a);
+        if (nt) hipLaunchKernelGGL((k_diag<false, true, kDiagU>), grid, dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_diag<false, false, kDiagU>), grid, dim3(kBlock), 0, st, a);
     }
     return hipGetLastError();
 }
