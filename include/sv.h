@@ -278,6 +278,15 @@ sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_t
  * its own stores and meets its own waves). Results are bit for bit those of the
  * level launches. max_tiles = 0 (the default) turns it off; at most 2^20. */
 sv_status sv_batch_persist(sv_batch b, int32_t max_tiles);
+/* Large circuits: a circuit whose passes have at least min_tiles tiles (and
+ * that the persistent launch does not take) runs pass by pass, one
+ * single-state launch per pass as sv_run_plan queues it (each such pass fills
+ * the device on its own), on a third stream of the batch, beside the levels
+ * and the persistent launch; these circuits run one after another, least work
+ * first, and their clocks for sv_batch_times are stamped before the first and
+ * after the last pass. Results are bit for bit those of the level launches.
+ * min_tiles = 0 (the default) turns it off. */
+sv_status sv_batch_solo(sv_batch b, int32_t min_tiles);
 /* Queues passes [first_pass[i], first_pass[i] + pass_count[i]) of plans[i],
  * i < count, on the batch's stream (first_pass NULL: from 0; pass_count NULL:
  * to the end). The plans' states must be distinct and of the batch's dtype;

@@ -24,7 +24,7 @@ __all__ = [
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
     "sv_plan_passes", "sv_run_plan", "sv_batch_create", "sv_batch_destroy", "sv_batch_config",
-    "sv_batch_persist", "sv_batch_run", "sv_batch_times", "StateVector", "LIB_PATH",
+    "sv_batch_persist", "sv_batch_solo", "sv_batch_run", "sv_batch_times", "StateVector", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsv.so")
@@ -101,6 +101,7 @@ _SIGNATURES = {
     "sv_batch_destroy": ([_vp], _int),
     "sv_batch_config": ([_vp, ctypes.c_int32, ctypes.c_int32], _int),
     "sv_batch_persist": ([_vp, ctypes.c_int32], _int),
+    "sv_batch_solo": ([_vp, ctypes.c_int32], _int),
     "sv_batch_run": ([_vp, _vp, _vp, _vp, _sz, _u32], _int),
     "sv_batch_times": ([_vp, _dp, _dp, _sz], _int),
     "sv_profile_read": ([_vp, ctypes.POINTER(_ProfEntry), _int, ctypes.POINTER(_int)], _int),
@@ -370,6 +371,12 @@ def sv_batch_persist(b: int, max_tiles: int) -> None:
     """Circuits of at most max_tiles tiles per pass run whole in one persistent
     launch (0: off)."""
     _check(lib().sv_batch_persist(b, int(max_tiles)))
+
+
+def sv_batch_solo(b: int, min_tiles: int) -> None:
+    """Circuits of at least min_tiles tiles per pass run pass by pass on a
+    third stream, beside the levels (0: off)."""
+    _check(lib().sv_batch_solo(b, int(min_tiles)))
 
 
 def sv_batch_config(b: int, blocks_per_cu: int, tiles_per_task: int) -> None:

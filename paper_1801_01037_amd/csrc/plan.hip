@@ -1409,6 +1409,12 @@ struct BatchImage {
     // circuit index of each entry, and where its table and clocks sit in `dev`.
     std::vector<int32_t> pcirc;
     size_t off_circ = 0, off_pstart = 0, off_pend = 0;
+    // Circuits run pass by pass with the single-state kernel (beside the
+    // levels): circuit index, its passes in `spasses` from sfirst[k] (scount[k]
+    // of them), and where its two clock stamps sit in `dev`.
+    std::vector<int32_t> scirc, sfirst, scount;
+    std::vector<svk::TileArgs> spasses;
+    size_t off_sstart = 0, off_send = 0;
 };
 
 struct sv_batch_s {
@@ -1421,6 +1427,10 @@ struct sv_batch_s {
     uint32_t tiles_per_task = 8;
     int32_t persist_tiles = 0;         // circuits of at most this many tiles per pass
                                        // run whole in the persistent launch (0: none)
+    int32_t solo_tiles = 0;            // circuits of at least this many tiles per pass
+                                       // run pass by pass on `solo` (0: none)
+    hipStream_t solo = nullptr;
+    hipEvent_t sfork = nullptr, sjoin = nullptr;
     BatchImage work;                   // runs without SV_GRAPH
     BatchImage gimg;                   // the captured graph's own buffers
     hipGraphExec_t gexec = nullptr;
@@ -1569,6 +1579,12 @@ sv_status sv_batch_destroy(sv_batch b)
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
+    if (b->solo) {
+        (void)hipStreamSynchronize(b->solo);
+        (void)hipStreamDestroy(b->solo);
+    }
+    if (b->sfork) (void)hipEventDestroy(b->sfork);
+    if (b->sjoin) (void)hipEventDestroy(b->sjoin);
     if (b->work.dev) (void)hipFree(b->work.dev);
     if (b->gimg.dev) (void)hipFree(b->gimg.dev);
     if (b->host) (void)hipHostFree(b->host);
@@ -1582,6 +1598,14 @@ sv_status sv_batch_persist(sv_batch b, int32_t max_tiles)
     if (!b) return berr(SV_EINVAL, "null batch");
     if (max_tiles < 0 || max_tiles > (1 << 20)) return berr(SV_EINVAL, "max_tiles out of range");
     b->persist_tiles = max_tiles;
+    return SV_OK;
+}
+
+sv_status sv_batch_solo(sv_batch b, int32_t min_tiles)
+{
+    if (!b) return berr(SV_EINVAL, "null batch");
+    if (min_tiles < 0) return berr(SV_EINVAL, "min_tiles is negative");
+    b->solo_tiles = min_tiles;
     return SV_OK;
 }
 
@@ -1661,6 +1685,26 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
             done[i] = cnt[i];
         }
     }
+    // Large circuits run pass by pass beside the levels, least work first.
+    img.scirc.clear();
+    img.sfirst.clear();
+    img.scount.clear();
+    img.spasses.clear();
+    if (b->solo_tiles > 0) {
+        std::vector<size_t> large;
+        for (size_t i = 0; i < count; ++i)
+            if (done[i] < cnt[i] && passes[pass0[i]].ntiles >= uint64_t(b->solo_tiles)) large.push_back(i);
+        std::stable_sort(large.begin(), large.end(), [&](size_t x, size_t y) {
+            return uint64_t(cnt[x]) * amps[x] < uint64_t(cnt[y]) * amps[y];
+        });
+        for (size_t i : large) {
+            img.scirc.push_back(int32_t(i));
+            img.sfirst.push_back(int32_t(img.spasses.size()));
+            img.scount.push_back(cnt[i]);
+            for (int32_t k = 0; k < cnt[i]; ++k) img.spasses.push_back(passes[pass0[i] + k]);
+            done[i] = cnt[i];
+        }
+    }
     std::vector<size_t> order;
     order.reserve(count);
     for (;;) {
@@ -1698,7 +1742,9 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     img.off_end = align_up(img.off_start + tasks.size() * sizeof(uint64_t), 256);
     img.off_pstart = align_up(img.off_end + tasks.size() * sizeof(uint64_t), 256);
     img.off_pend = align_up(img.off_pstart + circs.size() * sizeof(uint64_t), 256);
-    const size_t total = align_up(img.off_pend + circs.size() * sizeof(uint64_t), 256);
+    img.off_sstart = align_up(img.off_pend + circs.size() * sizeof(uint64_t), 256);
+    img.off_send = align_up(img.off_sstart + img.scirc.size() * sizeof(uint64_t), 256);
+    const size_t total = align_up(img.off_send + img.scirc.size() * sizeof(uint64_t), 256);
     const size_t upload = img.off_start;
     hipError_t e = hipEventSynchronize(b->staged);   // staging free again
     if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
@@ -1729,6 +1775,12 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     return SV_OK;
 }
 
+// Device clock (the one the level tasks stamp) at this point of the stream.
+__global__ void k_stamp(uint64_t *slot)
+{
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+
 // Queues the persistent launch (if any circuit takes it) on the side stream,
 // forked from `st` after the upload and joined back at the end, and one launch
 // per level of `img` on `st`: the two work on disjoint states, so the short
@@ -1757,6 +1809,26 @@ sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
         if (e == hipSuccess) e = hipEventRecord(b->join, b->side);
         if (e != hipSuccess) return berr(SV_EDEVICE, std::string("persistent launch: ") + hipGetErrorString(e));
     }
+    const bool solo = !img.scirc.empty();
+    if (solo) {
+        if (!b->solo || !b->sfork || !b->sjoin) return berr(SV_EDEVICE, "third stream not set up");
+        hipError_t e = hipEventRecord(b->sfork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->solo, b->sfork, 0);
+        uint64_t *t0 = reinterpret_cast<uint64_t *>(d + img.off_sstart);
+        uint64_t *t1 = reinterpret_cast<uint64_t *>(d + img.off_send);
+        for (size_t k = 0; k < img.scirc.size() && e == hipSuccess; ++k) {
+            hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, b->solo, t0 + k);
+            e = hipGetLastError();
+            for (int32_t j = 0; j < img.scount[k] && e == hipSuccess; ++j)
+                e = launch_tile(img.spasses[size_t(img.sfirst[k] + j)], 4, b->dt == SV_C64, b->solo);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, b->solo, t1 + k);
+                e = hipGetLastError();
+            }
+        }
+        if (e == hipSuccess) e = hipEventRecord(b->sjoin, b->solo);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("large circuits: ") + hipGetErrorString(e));
+    }
     BatchArgs a{};
     a.tasks = reinterpret_cast<const BatchTask *>(d);
     a.passes = reinterpret_cast<const TileArgs *>(d + img.off_pass);
@@ -1771,6 +1843,10 @@ sv_status launch_levels(sv_batch b, const BatchImage &img, hipStream_t st)
     if (side) {
         hipError_t e = hipStreamWaitEvent(st, b->join, 0);
         if (e != hipSuccess) return berr(SV_EDEVICE, std::string("side join: ") + hipGetErrorString(e));
+    }
+    if (solo) {
+        hipError_t e = hipStreamWaitEvent(st, b->sjoin, 0);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("third stream join: ") + hipGetErrorString(e));
     }
     return SV_OK;
 }
@@ -1791,6 +1867,7 @@ sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pa
     key.push_back(uintptr_t(b->blocks_per_cu));
     key.push_back(uintptr_t(b->tiles_per_task));
     key.push_back(uintptr_t(b->persist_tiles));
+    key.push_back(uintptr_t(b->solo_tiles));
     for (size_t i = 0; i < count; ++i) {
         const sv_plan p = plans[i];
         if (!p) return berr(SV_EINVAL, "null plan in batch");
@@ -1811,6 +1888,13 @@ sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pa
         if (e == hipSuccess && !b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
         if (e == hipSuccess && !b->join) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
         if (e != hipSuccess) return berr(SV_EDEVICE, std::string("side stream: ") + hipGetErrorString(e));
+    }
+    if (b->solo_tiles > 0) {      // so do the third stream and its events
+        hipError_t e = hipSuccess;
+        if (!b->solo) e = hipStreamCreateWithFlags(&b->solo, hipStreamNonBlocking);
+        if (e == hipSuccess && !b->sfork) e = hipEventCreateWithFlags(&b->sfork, hipEventDisableTiming);
+        if (e == hipSuccess && !b->sjoin) e = hipEventCreateWithFlags(&b->sjoin, hipEventDisableTiming);
+        if (e != hipSuccess) return berr(SV_EDEVICE, std::string("third stream: ") + hipGetErrorString(e));
     }
     if (!(flags & SV_GRAPH)) {
         if (sv_status st = prepare_batch(b, b->work, plans, first, cnt, b->stream)) return st;
@@ -1860,11 +1944,13 @@ sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t co
     if (!b) return berr(SV_EINVAL, "null batch");
     const BatchImage *img = b->last;
     if (!img || count != img->count) return berr(SV_EINVAL, "count differs from the last run");
-    const size_t nt = img->task_circ.size(), np = img->pcirc.size();
-    // Task clocks, then the persistent circuits' clocks, as one list.
-    std::vector<uint64_t> t0(nt + np), t1(nt + np);
+    const size_t nt = img->task_circ.size(), np = img->pcirc.size(), ns = img->scirc.size();
+    // Task clocks, the persistent circuits' clocks and the large circuits'
+    // stamps, as one list.
+    std::vector<uint64_t> t0(nt + np + ns), t1(nt + np + ns);
     std::vector<int32_t> circ_of(img->task_circ);
     circ_of.insert(circ_of.end(), img->pcirc.begin(), img->pcirc.end());
+    circ_of.insert(circ_of.end(), img->scirc.begin(), img->scirc.end());
     hipError_t e = hipSuccess;
     char *dev = static_cast<char *>(img->dev);
     if (nt) {
@@ -1881,13 +1967,20 @@ sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t co
             e = hipMemcpyAsync(t1.data() + nt, dev + img->off_pend, np * sizeof(uint64_t),
                                hipMemcpyDeviceToHost, b->stream);
     }
+    if (ns && e == hipSuccess) {
+        e = hipMemcpyAsync(t0.data() + nt + np, dev + img->off_sstart, ns * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t1.data() + nt + np, dev + img->off_send, ns * sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, b->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return berr(SV_EDEVICE, hipGetErrorString(e));
     const int khz = svk::wall_clock_khz();
     uint64_t origin = ~uint64_t(0);
-    for (size_t k = 0; k < nt + np; ++k) origin = std::min(origin, t0[k]);
+    for (size_t k = 0; k < nt + np + ns; ++k) origin = std::min(origin, t0[k]);
     std::vector<uint64_t> first(count, ~uint64_t(0)), last(count, 0);
-    for (size_t k = 0; k < nt + np; ++k) {
+    for (size_t k = 0; k < nt + np + ns; ++k) {
         const int32_t c = circ_of[k];
         first[c] = std::min(first[c], t0[k]);
         last[c] = std::max(last[c], t1[k]);

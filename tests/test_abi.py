@@ -58,6 +58,7 @@ def test_rejects_bad_arguments_without_a_device(lib):
     assert lib.sv_run_batch(one, one, lens, 1, 0x100) == sv.SV_EINVAL
     assert "flags" in sv.sv_last_error()
     assert lib.sv_run_batch(one, one, lens, 1, sv.SV_FUSE) == sv.SV_EINVAL   # null state
+    assert lib.sv_batch_solo(None, 4) == sv.SV_EINVAL
     assert lib.sv_norm(None, None) == sv.SV_EINVAL
     assert lib.sv_synchronize(None) == sv.SV_EINVAL
     with pytest.raises(sv.SVError) as ei:

@@ -345,3 +345,46 @@ def test_run_batch_rejects_before_running():
     finally:
         sv.sv_destroy(a)
         sv.sv_destroy(b)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
+@pytest.mark.parametrize("flags", [0, sv.SV_GRAPH], ids=["direct", "graph"])
+def test_large_circuits_on_a_third_stream(dtype, flags):
+    """sv_batch_solo: circuits of at least 4 tiles per pass (n >= 14) run pass
+    by pass on a third stream while 2-tile circuits take the levels and 1-tile
+    ones the persistent launch. Two runs in a row (the second a graph replay
+    under SV_GRAPH); every result equals the circuit run alone, and every
+    circuit has clocks."""
+    specs = [(14, 20, 1301), (16, 8, 1302), (15, 12, 1303), (10, 30, 1304),
+             (12, 10, 1305), (13, 16, 1306), (13, 6, 1307), (14, 0, 1308)]
+    circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_persist(b, 1)
+        sv.sv_batch_solo(b, 4)
+        for _ in range(2):
+            for h, (n, _, s) in zip(states, specs):
+                sv.sv_reset(h, qc.random_basis_index(n, s))
+            sv.sv_batch_run(b, plans, flags=flags)
+            start, end = sv.sv_batch_times(b, len(plans))
+            outs = [sv.sv_copy_out(h) for h in states]
+            for (n, d, s), g, got, t0, t1 in zip(specs, circuits, outs, start, end):
+                h = sv.sv_create(n, dtype)
+                try:
+                    sv.sv_reset(h, qc.random_basis_index(n, s))
+                    sv.sv_run_circuit(h, g, sv.SV_FUSE)
+                    want = sv.sv_copy_out(h)
+                finally:
+                    sv.sv_destroy(h)
+                assert np.array_equal(got, want), (n, d)
+                assert 0.0 <= t0 <= t1, (n, d, t0, t1)
+                if d:
+                    assert t1 > 0.0, (n, d)
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
