@@ -23,10 +23,14 @@ def _alone(r):
         sv.sv_destroy(h)
 
 
-def test_each_result_is_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("persist,solo", [(0, 2048), (1, 8)], ids=["default", "three-streams"])
+def test_each_result_is_the_same_alone_and_in_the_mix(persist, solo):
+    """Also with each step's batch split three ways: circuits of one tile per
+    pass (n <= 12) in the persistent launch, of 8 tiles or more (n >= 15) pass
+    by pass on the third stream, the rest in levels."""
     reqs = serving.poisson_requests(rate=400.0, count=24, seed=3, n_lo=10, n_hi=17,
                                     d_lo=5, d_hi=40)
-    srv = serving.Server(chunk=3, keep_results=True)
+    srv = serving.Server(chunk=3, keep_results=True, persist_tiles=persist, solo_tiles=solo)
     try:
         stats = srv.run(reqs)
     finally:
