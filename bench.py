@@ -203,11 +203,11 @@ def run_batched(sv, torch, count, seed=3):
     try:
         sv.sv_batch_config(b, bpc, tpt)
         # Circuits of at most 16 tiles per pass (n <= 16) run whole in the
-        # persistent launch on the batch's second stream, circuits of at least
-        # 2048 tiles per pass (n >= 23) pass by pass on its third stream, both
-        # beside the level launches that take the rest.
+        # persistent launch on the batch's second stream, circuits of 4096
+        # tiles per pass (n = 24) pass by pass on its third stream, both beside
+        # the level launches that take the rest.
         sv.sv_batch_persist(b, 16)
-        sv.sv_batch_solo(b, 2048)
+        sv.sv_batch_solo(b, 4096)
         for st in states:
             st.reset(0)
         sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)      # capture + first replay (warm-up)
@@ -250,7 +250,7 @@ def run_batched(sv, torch, count, seed=3):
     return {"circuits": count, "gates": gates, "dtype": "f32",
             "workload": "layered Haar-SU(2)/CNOT circuits, n ~ U{10..24}, depth ~ U{20..200}, "
                         "complex64, one batch replayed from a HIP graph: circuits of n <= 16 in a "
-                        "persistent launch on a second stream, n >= 23 pass by pass on a third, "
+                        "persistent launch on a second stream, n = 24 pass by pass on a third, "
                         "the others in level launches",
             "p50_ms": round(float(np.percentile(end, 50)), 3),
             "p99_ms": round(float(np.percentile(end, 99)), 3),
@@ -262,8 +262,8 @@ def run_batched(sv, torch, count, seed=3):
             "norm_max_dev": max(abs(x - 1.0) for x in norms),
             "persistent": {"max_tiles": 16,
                            "circuits": int(sum(1 for n, _, _ in specs if max(1, 2 ** (n - 12)) <= 16))},
-            "pass_by_pass": {"min_tiles": 2048,
-                             "circuits": int(sum(1 for n, _, _ in specs if 2 ** (n - 12) >= 2048))},
+            "pass_by_pass": {"min_tiles": 4096,
+                             "circuits": int(sum(1 for n, _, _ in specs if 2 ** (n - 12) >= 4096))},
             "levels_only": levels_only}
 
 

@@ -12,7 +12,7 @@ import os
 
 import paper_1801_01037_amd as sv
 
-CANDIDATES = ((1, 1), (1, 8), (2, 1), (2, 4), (2, 8), (2, 32), (4, 8), (4, 64))
+CANDIDATES = ((1, 1), (1, 8), (2, 1), (2, 4), (2, 8), (2, 32), (3, 4), (3, 8), (3, 16), (4, 8), (4, 64))
 
 
 def cache_path() -> str:

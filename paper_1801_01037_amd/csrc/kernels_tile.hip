@@ -622,7 +622,8 @@ __global__ __launch_bounds__(MAXT) void k_tile(TileArgs a)
 // orders consecutive levels of a circuit. Each task stores its start and end
 // device clock.
 template <bool C64, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(C64 ? 3 : 1)))
+void k_level(BatchArgs b)
 {
     using A = AmpT<C64>;
     constexpr int K = 4;
@@ -655,7 +656,8 @@ __global__ __launch_bounds__(MAXT) void k_level(BatchArgs b)
 // made the compiler split this loop around that lane: the other lanes then
 // ran the same circuit again without end.)
 template <bool C64, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_persist(PersistArgs p)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(C64 ? 3 : 1)))
+void k_persist(PersistArgs p)
 {
     using A = AmpT<C64>;
     constexpr int K = 4;
