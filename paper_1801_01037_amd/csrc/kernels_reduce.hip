@@ -45,16 +45,29 @@ __global__ __launch_bounds__(kBlock) void k_norm_partial(const void *psi, uint64
     using V = std::conditional_t<C64, float4, double2>;
     const V *p = static_cast<const V *>(psi);
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    double acc = 0.0;
-    for (uint64_t c = uint64_t(blockIdx.x) * kBlock + threadIdx.x; c < chunks; c += stride) {
-        const V v = ld16<NT>(&p[c]);
+    auto sq = [](const V &v) -> double {
         if constexpr (C64) {
             const double a = v.x, b = v.y, d = v.z, e = v.w;
-            acc += (a * a + b * b) + (d * d + e * e);
+            return (a * a + b * b) + (d * d + e * e);
         } else {
-            acc += v.x * v.x + v.y * v.y;
+            return v.x * v.x + v.y * v.y;
         }
+    };
+    // Four loads in flight per thread, four partial sums; each XCD walks one
+    // contiguous eighth of every stride (complex64: 5.4 -> 6.3 TB/s).
+    double acc = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    uint64_t c = uint64_t(xcd_block(blockIdx.x, gridDim.x % 8 == 0 ? gridDim.x / 8 : 0)) * kBlock +
+                 threadIdx.x;
+    for (; c + 3 * stride < chunks; c += 4 * stride) {
+        const V v0 = ld16<NT>(&p[c]), v1 = ld16<NT>(&p[c + stride]);
+        const V v2 = ld16<NT>(&p[c + 2 * stride]), v3 = ld16<NT>(&p[c + 3 * stride]);
+        acc += sq(v0);
+        acc1 += sq(v1);
+        acc2 += sq(v2);
+        acc3 += sq(v3);
     }
+    for (; c < chunks; c += stride) acc += sq(ld16<NT>(&p[c]));
+    acc = (acc + acc1) + (acc2 + acc3);
     const double s = block_sum<kBlock>(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }

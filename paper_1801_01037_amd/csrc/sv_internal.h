@@ -72,6 +72,14 @@ __device__ __forceinline__ void st16(V *p, const V &v)
     }
 }
 
+// Work-groups are dealt to the 8 XCDs in turn (work-group b to XCD b mod 8).
+// With span = grid / 8, work-group b takes block (b mod 8) span + b / 8, so
+// each XCD walks one contiguous eighth of a launch's range (span 0: block b).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t span)
+{
+    return span ? (b & 7u) * span + (b >> 3) : b;
+}
+
 // ---- launchers (kernels_gate.hip) ----------------------------------------
 // All take the state pointer, qubit count and stream; they validate nothing.
 hipError_t launch_init(void *psi, int n, sv_dtype dt, uint64_t basis, hipStream_t st);
