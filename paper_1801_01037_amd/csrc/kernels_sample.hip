@@ -41,11 +41,24 @@ template <bool C64>
 __global__ __launch_bounds__(kThreads) void k_block_sums(const void *psi, uint64_t nb, int bsize,
                                                           double *S)
 {
+    using V = std::conditional_t<C64, float4, double2>;   // one 16-byte chunk
+    constexpr int E = C64 ? 2 : 1;
+    const V *p = static_cast<const V *>(psi);
     __shared__ double part[kThreads];
-    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const uint64_t base = b * uint64_t(bsize);
+    // Each XCD takes one contiguous eighth of every round of blocks.
+    const uint64_t b0 = xcd_block(blockIdx.x, gridDim.x % 8 == 0 ? gridDim.x / 8 : 0);
+    for (uint64_t b = b0; b < nb; b += gridDim.x) {
+        const uint64_t base = b * uint64_t(bsize / E);
         double s = 0.0;
-        for (int k = threadIdx.x; k < bsize; k += kThreads) s += prob_at<C64>(psi, base + k);
+        for (int k = threadIdx.x; k < bsize / E; k += kThreads) {
+            const V v = p[base + k];
+            if constexpr (C64) {
+                const double a = v.x, c = v.y, d = v.z, e = v.w;
+                s += (a * a + c * c) + (d * d + e * e);
+            } else {
+                s += v.x * v.x + v.y * v.y;
+            }
+        }
         part[threadIdx.x] = s;
         __syncthreads();
         for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -176,14 +189,15 @@ __global__ __launch_bounds__(kThreads) void k_sample(const void *psi, uint64_t n
 template <bool C64>
 __global__ __launch_bounds__(kThreads) void k_fill(void *psi, uint64_t count, double value)
 {
-    using A = std::conditional_t<C64, float2, double2>;
-    using R = std::conditional_t<C64, float, double>;
-    A v;
-    v.x = R(value);
-    v.y = R(0);
-    A *p = static_cast<A *>(psi);
-    for (uint64_t i = uint64_t(blockIdx.x) * kThreads + threadIdx.x; i < count;
-         i += uint64_t(gridDim.x) * kThreads)
+    // count: 16-byte chunks (two complex64 or one complex128 amplitude each);
+    // each XCD writes one contiguous eighth of every grid stride.
+    using V = std::conditional_t<C64, float4, double2>;
+    V v;
+    if constexpr (C64) v = make_float4(float(value), 0.f, float(value), 0.f);
+    else v = make_double2(value, 0.0);
+    V *p = static_cast<V *>(psi);
+    const uint64_t b = xcd_block(blockIdx.x, gridDim.x % 8 == 0 ? gridDim.x / 8 : 0);
+    for (uint64_t i = b * kThreads + threadIdx.x; i < count; i += uint64_t(gridDim.x) * kThreads)
         p[i] = v;
 }
 
@@ -223,7 +237,7 @@ hipError_t launch_sample(const void *psi, int n, sv_dtype dt, const double *S, c
 
 hipError_t launch_fill(void *psi, int n, sv_dtype dt, double value, hipStream_t st)
 {
-    const uint64_t count = uint64_t(1) << n;
+    const uint64_t count = (uint64_t(1) << n) >> chunk_log2(dt);   // n >= 1: whole chunks
     const unsigned grid = grid_of((count + kThreads - 1) / kThreads, 8192);
     if (dt == SV_C64) hipLaunchKernelGGL(k_fill<true>, dim3(grid), dim3(kThreads), 0, st, psi, count, value);
     else hipLaunchKernelGGL(k_fill<false>, dim3(grid), dim3(kThreads), 0, st, psi, count, value);
