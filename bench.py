@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-pergate", action="store_true",
+                    help="skip the per-gate 1q pass timings on six targets")
     ap.add_argument("--batched-circuits", type=int, default=512)
     ap.add_argument("--serving-arrivals", type=int, default=64,
                     help="arrivals of each serving sample (0: no serving sample)")
@@ -291,6 +293,27 @@ def _stats(ms, nbytes):
             "GBps": round(nbytes / (med * 1e-3) / 1e9, 1)}
 
 
+def run_pergate_1q(sv, torch, n, reps=10, targets=(0, 5, 11, 17, 23, 29)):
+    """A Haar 2x2 gate alone on each of a few targets at n qubits (one pass of
+    the state per gate), per dtype: algorithmic GB/s (2 N s per gate) and its
+    fraction of the 8 TB/s HBM peak, median of `reps` HIP-event timings."""
+    import qcircuits as qc
+    out = {}
+    for dt, tag, sb in ((sv.SV_C128, "c128", 16), (sv.SV_C64, "c64", 8)):
+        st = sv.StateVector(n, dt)
+        try:
+            u = qc.haar_su2(5, 1)[0]
+            gbps = [_stats(_event_times(torch, st.stream, lambda q=q: st.apply_1q(q, u), reps),
+                           2 * 2.0 ** n * sb)["GBps"] for q in targets if q < n]
+        finally:
+            st.close()
+            torch.cuda.empty_cache()
+        fr = np.asarray(gbps) / HBM_PEAK_GBS
+        out[tag] = {"targets": [q for q in targets if q < n], "GBps": gbps,
+                    "frac_min": round(float(fr.min()), 4), "frac_median": round(float(np.median(fr)), 4)}
+    return out
+
+
 def run_sweep(sv, torch, n, reps):
     """Per-gate timings at n qubits: a Haar 2x2 on every qubit, CNOT on
     neighbours and on (0, n-1) both ways, controlled phases, and general
@@ -457,6 +480,10 @@ def main():
                    "effective_hbm_frac": round(r64["effective_hbm_frac"], 4),
                    "speedup_vs_c128": round(r64["gates_per_s"] / r128["gates_per_s"], 3),
                    "roofline": roofline(r64["profile"], "c64"), "norm": r64["norm"]}
+    pergate = None
+    if not args.no_pergate and args.mode == "fused":
+        log("[bench] per-gate 1q passes")
+        pergate = run_pergate_1q(sv, torch, n)
     batched = None
     if not args.no_batched:
         log(f"[bench] batched: {args.batched_circuits} circuits")
@@ -498,6 +525,7 @@ def main():
         "roofline": roofline(r128["profile"], "c128"),
         "cpu_baseline": cpu,
         "c64": out_c64,
+        "pergate_1q": pergate,
         "batched": batched,
         "serving": serving_stats,
         "kernels_c128": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3),

@@ -184,7 +184,8 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
  * sv_run_circuit(states[c], circuits[c], lens[c], SV_FUSE) bit for bit.
  * States must be distinct and may mix dtypes, sizes and streams. Circuits on
  * n >= 4 qubits without several-control gates go into one batch per dtype
- * (see sv_batch_run: default launch configuration), queued on the stream of
+ * (see sv_batch_run: default launch configuration, circuits of 4096 tiles per
+ * pass and more, n >= 24, pass by pass as sv_batch_solo), queued on the stream of
  * that dtype's first such state after the earlier work of every member's
  * stream; the others run alone with SV_FUSE. flags: 0, SV_FUSE (the same) and
  * optionally SV_GRAPH (each batch captured and replayed). Synchronous: returns
@@ -265,8 +266,8 @@ sv_status sv_run_plan(sv_plan p, int32_t first_pass, int32_t count);
  * not run twice at the same time; distinct batches may. */
 sv_status sv_batch_create(sv_dtype dtype, void *hip_stream, sv_batch *out);
 sv_status sv_batch_destroy(sv_batch b);
-/* Tuning: work-groups per CU of each level launch (1..8, default 2) and tiles
- * per task (1..4096, default 8). */
+/* Tuning: work-groups per CU of each level launch (1..8) and tiles per task
+ * (1..4096); defaults 3 and 4 for complex64, 2 and 8 for complex128. */
 sv_status sv_batch_config(sv_batch b, int32_t blocks_per_cu, int32_t tiles_per_task);
 /* Persistent launch for small circuits: a circuit whose passes have at most
  * max_tiles tiles (2^(n-12) for n > 12, one below) runs whole, every pass in

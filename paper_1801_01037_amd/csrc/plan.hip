@@ -1559,6 +1559,12 @@ sv_status sv_batch_create(sv_dtype dtype, void *hip_stream, sv_batch *out)
     if (!b) return berr(SV_ENOMEM, "host allocation failed");
     b->dt = dtype;
     b->stream = static_cast<hipStream_t>(hip_stream);
+    // Complex64 batch kernels hold three work-groups per CU, complex128 ones
+    // two (the tuned configurations of the 512-circuit batch: 3x4 for complex64).
+    if (dtype == SV_C64) {
+        b->blocks_per_cu = 3;
+        b->tiles_per_task = 4;
+    }
     if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
         delete b;
         return berr(SV_EDEVICE, "event creation failed");

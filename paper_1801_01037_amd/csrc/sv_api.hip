@@ -490,6 +490,7 @@ sv_status sv_run_batch(sv_state *states, const sv_gate *const *circuits, const s
         }
         sv_batch b = nullptr;
         result = sv_batch_create(d == 0 ? SV_C64 : SV_C128, lead->stream, &b);
+        if (result == SV_OK) result = sv_batch_solo(b, 4096);   // 24+ qubits pass by pass
         if (result == SV_OK)
             result = sv_batch_run(b, plans[d].data(), nullptr, nullptr, plans[d].size(), flags & SV_GRAPH);
         if (b) {
