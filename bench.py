@@ -8,7 +8,8 @@ One step runs the whole hot path once over the 30-qubit workload:
 The state lives in HBM the whole time (complex128: 16 GiB; complex64: 8 GiB).
 `value` is gates per second over the timed steps in complex128 (the paper's
 precision); the complex64 run of the same steps is reported beside it.
-Beside the steps (untimed for `value`): a batch of 512 circuits (p50/p99
+Beside the steps (untimed for `value`): a Haar 2x2 gate alone on six targets
+(per-gate passes against the HBM peak), a batch of 512 circuits (p50/p99
 latency), serving samples at the offered rates of --serving-rates, and the
 oracle on the host cores as the CPU baseline.
 

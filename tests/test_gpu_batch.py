@@ -285,10 +285,12 @@ def test_persist_rejects_bad_values():
         sv.sv_batch_destroy(b)
 
 
-def test_run_batch_one_call_mixed_states():
+@pytest.mark.parametrize("flags", [sv.SV_FUSE, sv.SV_FUSE | sv.SV_GRAPH], ids=["direct", "graph"])
+def test_run_batch_one_call_mixed_states(flags):
     """sv_run_batch: complex64 and complex128 states of several sizes and
     streams, a circuit with a Toffoli and one on 3 qubits (both run alone), an
-    empty circuit; every result equals the circuit run alone with SV_FUSE."""
+    empty circuit, a 24-qubit circuit (pass by pass on the batch's third
+    stream); every result equals the circuit run alone with SV_FUSE."""
     import torch
     side = torch.cuda.Stream()
     cases = [(12, sv.SV_C128, qc.layer_circuit(12, 6, 71), None),
@@ -299,12 +301,13 @@ def test_run_batch_one_call_mixed_states():
              (3, sv.SV_C128, qc.layer_circuit(3, 5, 75), None),
              (9, sv.SV_C128, qc.layer_circuit(9, 0, 76), None),
              (16, sv.SV_C128, qc.qft_circuit(16), side.cuda_stream),
-             (11, sv.SV_C64, qc.qft_circuit(11), None)]
+             (11, sv.SV_C64, qc.qft_circuit(11), None),
+             (24, sv.SV_C64, qc.layer_circuit(24, 2, 77), None)]
     states = [sv.sv_create(n, dt, st) for n, dt, _, st in cases]
     try:
         for h, (n, _, _, _) in zip(states, cases):
             sv.sv_reset(h, qc.random_basis_index(n, 700 + n))
-        sv.sv_run_batch(states, [g for _, _, g, _ in cases], sv.SV_FUSE)
+        sv.sv_run_batch(states, [g for _, _, g, _ in cases], flags)
         outs = [sv.sv_copy_out(h) for h in states]
     finally:
         for h in states:
