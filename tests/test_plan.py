@@ -179,3 +179,17 @@ def test_no_relabel_needs_fuse():
     with pytest.raises(sv.SVError) as e:
         sv.sv_plan_inspect(5, sv.SV_C128, g, sv.SV_FUSE_DENSE | sv.SV_NO_RELABEL)
     assert e.value.status == sv.SV_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype,shape", [
+    (sv.SV_C128, {"qft": (3, 9, 59), "layers": (16, 93, 375)}),
+    (sv.SV_C64, {"qft": (4, 8, 59), "layers": (18, 90, 382)}),
+], ids=["c128", "c64"])
+def test_benchmark_plans_do_not_grow(dtype, shape):
+    """The plans of the 30-qubit benchmark step (QFT, depth-20 layers) keep
+    at most the passes, register groups and ops they have now: a planner
+    change that makes them longer shows here before it shows in the timings."""
+    for name, g in (("qft", qc.qft_circuit(30)), ("layers", qc.layer_circuit(30, 20, 1))):
+        _, passes, groups, ops = sv.sv_plan_inspect(30, dtype, g, sv.SV_FUSE)
+        p0, g0, o0 = shape[name]
+        assert passes <= p0 and groups <= g0 and ops <= o0, (name, passes, groups, ops)
