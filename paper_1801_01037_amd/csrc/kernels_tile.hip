@@ -531,6 +531,10 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
         lds_barrier();
         for (int gi = 0; gi < a.ngroups; ++gi) {
             CGroup &G = groups[a.group0 + gi];
+            // Waves applying a group's ops issue ahead of the other work-group's
+            // waves that exchange through LDS or move tiles (layered step
+            // -1.8 %, QFT -2.5 % for complex128; -1.7 % / -4.4 % complex64).
+            __builtin_amdgcn_s_setprio(2);
             if (active) {
                 uint32_t lbase = 0;
                 for (int k = 0; k < a.L - K; ++k) lbase |= ((tid >> k) & 1u) << G.ns[k];
@@ -574,6 +578,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                     apply_op<C64, K>(w, v, li, ops[G.op0 + oi + 1], dtab, a.L, G, g, gbase, tid, tab);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             lds_barrier();
         }
         // Each thread stores the slots it filled, so the next fill needs no
