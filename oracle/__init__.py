@@ -10,6 +10,9 @@ Two tiers:
     by gate, at any n that fits host memory;
   * brute-force tier (`oracle.dense`, numpy): dense Kronecker-product
     operators for n <= 10 (the paper's direct approach).
+Threads: `set_threads(k)` switches to the OpenMP build of the same C source
+for k > 1 (the loops of each gate shared among k threads, the same bits as
+the single-threaded reference build, which is the default).
 Closed forms used as pins or as sampled references at large n:
   * `qft_basis_amplitude` (QFT of |x>), `product_state_amplitude` (circuits
     of one-qubit gates only, equation circuit-level), `uniform_amplitude`
@@ -47,16 +50,45 @@ def load(path: str):
     L.orc_norm.restype = ctypes.c_double
     L.orc_qft_basis_amplitude.argtypes = [ctypes.c_int, ctypes.c_uint64,
                                           ctypes.c_uint64, dp]
+    L.orc_threads.argtypes = [ctypes.c_int]
+    L.orc_threads.restype = ctypes.c_int
     return L
 
 
+_ref = None
+_omp = None
+
+
+def _built(path):
+    if not os.path.exists(path):
+        build_oracle.build()
+    return load(path)
+
+
 def lib():
-    global _lib
+    """The library the functions below call (the single-threaded reference
+    build unless set_threads chose the OpenMP one)."""
+    global _lib, _ref
     if _lib is None:
-        if not os.path.exists(build_oracle.LIB):
-            build_oracle.build()
-        _lib = load(build_oracle.LIB)
+        if _ref is None:
+            _ref = _built(build_oracle.LIB)
+        _lib = _ref
     return _lib
+
+
+def set_threads(k: int) -> int:
+    """k <= 1: the single-threaded reference build; k > 1: the OpenMP build
+    with k threads. Returns the number of threads in effect."""
+    global _lib, _ref, _omp
+    if k <= 1:
+        if _ref is None:
+            _ref = _built(build_oracle.LIB)
+        _lib = _ref
+        return 1
+    if _omp is None:
+        _omp = _built(build_oracle.LIB_OMP)
+    _lib = _omp
+    return int(_omp.orc_threads(int(k)))
 
 
 def _dp(a: np.ndarray):

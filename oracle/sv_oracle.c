@@ -32,11 +32,36 @@
  *
  * Arithmetic: every complex product is written out in real arithmetic and the
  * file is built with -ffp-contract=off, so each operation rounds once.
- * Single-threaded on purpose: it is the plain reference, not a fast path.
+ *
+ * Threads: the reference build (liboracle.so) is single-threaded. The same
+ * source built with -fopenmp (liboracle_omp.so) shares the iterations of
+ * Algorithm 1's two loops, taken together, among threads (the loops of the
+ * paper's Multi-Threading section). The pairs of one gate are disjoint and each
+ * is updated by the same operations in the same order, so both builds give
+ * the same bits; reductions (the norm) stay sequential. It serves as the all-core
+ * CPU baseline and to run large reference circuits.
  */
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Loops over fewer iterations than this stay on one thread. */
+#define ORC_PAR_MIN 4096
+
+/* Work-sharing in the OpenMP build (nothing in the reference build):
+ * ORC_FOR2 shares the iterations of Algorithm 1's two nested loops, taken
+ * together, among the threads; ORC_FOR those of a single loop. Both only when
+ * the flag `orc_par` in scope holds (enough work to share). */
+#ifdef _OPENMP
+#define ORC_FOR2 _Pragma("omp parallel for collapse(2) if(orc_par)")
+#define ORC_FOR _Pragma("omp parallel for schedule(static) if(orc_par)")
+#else
+#define ORC_FOR2
+#define ORC_FOR
+#endif
 
 #define ORC_TWO_PI 6.283185307179586476925286766559
 
@@ -59,6 +84,9 @@ enum { ORC_U = 0, ORC_CU = 1, ORC_CPHASE = 2, ORC_MCU = 3 };
 void orc_init_basis(double *psi, int n, uint64_t x)
 {
     uint64_t N = (uint64_t)1 << n;
+    const int orc_par = N >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR
     for (uint64_t i = 0; i < 2 * N; ++i)
         psi[i] = 0.0;
     psi[2 * x] = 1.0;
@@ -84,6 +112,9 @@ void orc_apply_1q(double *psi, int n, int t, const double m[8])
 {
     uint64_t N = (uint64_t)1 << n;
     uint64_t stride = (uint64_t)1 << t;
+    const int orc_par = N >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR2
     for (uint64_t j = 0; j < N; j += 2 * stride)
         for (uint64_t k = j; k < j + stride; ++k)
             pair_update(psi + 2 * k, psi + 2 * (k + stride), m);
@@ -96,6 +127,9 @@ void orc_apply_ctrl(double *psi, int n, int c, int t, const double m[8])
     uint64_t N = (uint64_t)1 << n;
     uint64_t stride = (uint64_t)1 << t;
     uint64_t cbit = (uint64_t)1 << c;
+    const int orc_par = N >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR2
     for (uint64_t j = 0; j < N; j += 2 * stride)
         for (uint64_t k = j; k < j + stride; ++k)
             if (k & cbit)
@@ -108,6 +142,9 @@ void orc_apply_mcu(double *psi, int n, uint64_t cmask, int t, const double m[8])
 {
     uint64_t N = (uint64_t)1 << n;
     uint64_t stride = (uint64_t)1 << t;
+    const int orc_par = N >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR2
     for (uint64_t j = 0; j < N; j += 2 * stride)
         for (uint64_t k = j; k < j + stride; ++k)
             if ((k & cmask) == cmask)
@@ -146,8 +183,11 @@ int orc_apply_unitary(double *psi, int n, const int *q, int k, const double *U)
             if ((c >> m) & 1u)
                 off[c] |= (uint64_t)1 << q[m];
     }
-    double a[128], out[128];
+    const int orc_par = G >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR
     for (uint64_t g = 0; g < G; ++g) {
+        double a[128], out[128];
         uint64_t base = g;             /* insert a zero at each qubit position */
         for (int m = 0; m < k; ++m) {
             uint64_t low = base & (((uint64_t)1 << sorted[m]) - 1);
@@ -180,6 +220,20 @@ void orc_apply_cphase(double *psi, int n, int c, int t, double theta)
 {
     double m[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, cos(theta), sin(theta)};
     orc_apply_ctrl(psi, n, c, t, m);
+}
+
+/* Threads the OpenMP build uses from now on (n >= 1); returns the number in
+ * effect. The reference build always runs one thread and returns 1. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Applies the gates in list order. Returns 0, or -1 on a malformed record. */
@@ -221,6 +275,9 @@ int orc_run_circuit(double *psi, int n, const orc_gate *g, size_t count)
 /* p_i = |alpha_i|^2 for i in [first, first + count). */
 void orc_probs(const double *psi, uint64_t first, uint64_t count, double *out)
 {
+    const int orc_par = count >= ORC_PAR_MIN;
+    (void)orc_par;
+    ORC_FOR
     for (uint64_t i = 0; i < count; ++i) {
         double re = psi[2 * (first + i)], im = psi[2 * (first + i) + 1];
         out[i] = re * re + im * im;

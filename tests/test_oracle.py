@@ -218,6 +218,72 @@ def test_norm_and_probs_against_exact_sums():
     assert oracle.probs(oracle.basis_state(5, 19))[19] == 1.0
 
 
+def test_probabilities_of_circuit_results_sum_to_one():
+    """A unitary circuit keeps the norm (section Quantum Information
+    Processing: the squared moduli of a state's amplitudes sum to one), so
+    the probabilities of its complex result must sum to 1."""
+    n = 9
+    psi = oracle.simulate(n, qc.workload_layers_qft(n, 6, 4))
+    assert np.abs(psi.imag).max() > 0.05          # a complex state
+    p = oracle.probs(psi)
+    assert abs(math.fsum(p) - 1.0) <= 1e-13
+    assert abs(math.fsum(oracle.probs(psi, 0, 200)) + math.fsum(oracle.probs(psi, 200))
+               - 1.0) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [3, 8, 11])
+def test_qft_probabilities_are_uniform(n):
+    """The QFT of a basis state spreads it evenly: every |alpha|^2 is 2^-n
+    (closed form of the transform; the amplitudes are complex, so a lost
+    real or imaginary square shows)."""
+    x = qc.random_basis_index(n, 31 + n)
+    psi = oracle.basis_state(n, x)
+    oracle.run_circuit(psi, qc.qft_circuit(n))
+    p = oracle.probs(psi)
+    assert np.max(np.abs(p - 2.0 ** -n)) <= 1e-15
+
+
+def test_product_state_probabilities_factorise():
+    """For one-qubit gates only, alpha_i is the product over qubits of each
+    qubit's own amplitude (equation circuit-level), so p_i is the product of
+    the per-qubit squared moduli."""
+    n = 7
+    g = np.concatenate([qc.gate_u(q % n, qc.haar_su2(50 + q, 1)[0]) for q in range(3 * n)])
+    psi = oracle.simulate(n, g, 5)
+    v = oracle.qubit_vectors(n, g, 5)
+    p = oracle.probs(psi)
+    for i in range(1 << n):
+        want = 1.0
+        for q in range(n):
+            want *= abs(v[q, (i >> q) & 1]) ** 2
+        assert abs(p[i] - want) <= 1e-14
+
+
+def test_openmp_build_gives_the_same_bits():
+    """The OpenMP build shares out the loops of each gate; every pair is
+    still updated by the same operations, so its results equal the
+    single-threaded build's bit for bit (gates on low and high targets take
+    the outer and the inner loop sharing)."""
+    n = 13
+    g = np.concatenate([_mixed_circuit(n, 300, 8), qc.workload_layers_qft(n, 4, 2)])
+    psi0 = qc.random_state(n, 12)
+    u = qc.random_unitary(3, 4)
+    outs = []
+    for k in (1, 4):
+        assert oracle.set_threads(k) == k
+        try:
+            psi = psi0.copy()
+            oracle.run_circuit(psi, g)
+            oracle.apply_unitary(psi, (11, 0, 6), u)
+            oracle.apply_mcu(psi, (2, 12), 7, qc.haar_su2(9, 1)[0])
+            outs.append((psi, oracle.probs(psi), oracle.norm(psi), oracle.basis_state(n, 77)))
+        finally:
+            oracle.set_threads(1)
+    a, b = outs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    assert np.array_equal(a[3], b[3])
+
+
 def test_controlled_gate_leaves_control_zero_half_untouched():
     n, c, t = 7, 4, 1
     rng = np.random.default_rng(1)

@@ -26,6 +26,9 @@ MUTANTS = {
     "conjugated_phase": [("cos(theta), sin(theta)", "cos(theta), -sin(theta)")],
     "qft_no_bit_reversal": [("<< (n - 1 - b);", "<< b;")],
     "norm_drops_imag": [("+ psi[2 * i + 1] * psi[2 * i + 1];", ";")],
+    "probs_drops_imag": [("out[i] = re * re + im * im;", "out[i] = re * re;")],
+    "probs_ignores_first": [("double re = psi[2 * (first + i)], im = psi[2 * (first + i) + 1];",
+                             "double re = psi[2 * i], im = psi[2 * i + 1];")],
     "mcu_any_control": [("if ((k & cmask) == cmask)", "if (k & cmask)")],
     "unitary_transposed": [("double ur = U[2 * (r * D + c)], ui = U[2 * (r * D + c) + 1];",
                             "double ur = U[2 * (c * D + r)], ui = U[2 * (c * D + r) + 1];")],
@@ -46,6 +49,9 @@ PINS = [
     pins.test_layer_and_qft_circuits_match_dense_tier,
     pins.test_product_state_rule,
     pins.test_norm_and_probs_against_exact_sums,
+    pins.test_probabilities_of_circuit_results_sum_to_one,
+    lambda: pins.test_qft_probabilities_are_uniform(8),
+    pins.test_product_state_probabilities_factorise,
     pins.test_controlled_gate_leaves_control_zero_half_untouched,
     pins.test_toffoli_truth_table,
     lambda: pins.test_mcu_stride_tier_matches_dense_tier((0, 2, 4), 5),
