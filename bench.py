@@ -26,10 +26,11 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-# MI355X vector peaks (256 CUs at 2.4 GHz): FP64 128 flop/clock/CU, FP32 256
-# flop/clock/CU (the FP32 figure counts packed FMA; without packed math the
-# FP32 rate equals the FP64 one).
-ALU_PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}
+# MI355X vector peaks (256 CUs at 2.4 GHz): FP64 128 flop/clock/CU. The
+# published FP32 figure (157.3 TFLOP/s, 256 flop/clock/CU) counts packed FP32
+# FMA; this library is built without packed FP32, so its FP32 vector rate is
+# the FP64 one, and that is the roof of the complex64 vector kernels.
+ALU_PEAK_TFLOPS = {"c128": 78.6, "c64": 78.6}
 # Dense MFMA peaks (FP64 and FP32 matrix instructions): the compute roof of the
 # dense-block kernel.
 MFMA_PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}
@@ -47,16 +48,20 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl"], default="fused",
+    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl", "cpu_sweep"],
+                    default="fused",
                     help="fused: SV_FUSE tile passes; pergate: one launch per gate; "
                          "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores; "
                          "sweep: per-gate timings on every qubit at 30 qubits; "
-                         "xl: the 33-qubit complex128 / 34-qubit complex64 depth-10 circuit")
+                         "xl: the 33-qubit complex128 / 34-qubit complex64 depth-10 circuit; "
+                         "cpu_sweep: the oracle's per-gate cost on the host (no GPU)")
     ap.add_argument("--reps", type=int, default=20, help="timed repetitions per gate (sweep)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error statement (complex64 against complex128 and the oracle)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pergate", action="store_true",
                     help="skip the per-gate 1q pass timings on six targets")
@@ -80,10 +85,39 @@ def workload(n):
     return x, qc.qft_circuit(n), qc.layer_circuit(n, 20, 1)
 
 
+def method_flops(gates, n):
+    """Floating-point operations the method itself needs for a gate list on
+    2^n amplitudes, gate by gate (the algorithmic work of the stride update,
+    not what a fused kernel happens to execute): a dense 2x2 gate 14 per
+    amplitude (28 per pair), a controlled dense 2x2 7 (half the pairs), a
+    diagonal one-qubit phase 3, a controlled phase 1.5 (a quarter of the
+    amplitudes, 6 each), X and CNOT 0 (pure exchanges)."""
+    N = float(2 ** n)
+    x = np.array([0, 0, 1, 0, 1, 0, 0, 0], dtype=np.float64)
+    total = 0.0
+    for g in gates:
+        kind, m = int(g["kind"]), np.asarray(g["m"], dtype=np.float64)
+        if kind == 2:
+            total += 1.5 * N
+        elif np.array_equal(m, x):
+            continue
+        elif kind == 0 and m[2] == m[3] == m[4] == m[5] == 0.0:
+            total += 3.0 * N
+        elif kind == 0:
+            total += 14.0 * N
+        elif kind == 1:
+            total += 7.0 * N
+        else:   # several controls: the pairs where all k are set, 2^-k of them
+            mask = (int(g["control"]) & 0xFFFFFFFF) | ((int(g["flags"]) & 0xFFFFFFFF) << 32)
+            total += 14.0 * N / 2 ** bin(mask).count("1")
+    return total
+
+
 def run_dtype(sv, torch, dtype, n, steps, warmup, flags):
     """Times `steps` steps; returns a result dict with per-class event timings."""
     x, qft, layers = workload(n)
     gates_per_step = len(qft) + len(layers)
+    flops_per_step = method_flops(qft, n) + method_flops(layers, n)
     st = sv.StateVector(n, dtype)
     probs = torch.empty(PROBS_COUNT, dtype=torch.float64, device="cuda")
     norm_out = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -120,6 +154,8 @@ def run_dtype(sv, torch, dtype, n, steps, warmup, flags):
         "ms_per_step": 1e3 * elapsed / steps,
         "gates_per_s": gates_per_step * steps / elapsed,
         "gates_per_step": gates_per_step,
+        "method_flops_per_step": flops_per_step,
+        "steps": steps,
         "norm": norm,
         "profile": prof,
         "effective_hbm_frac": alg_bytes / elapsed / (HBM_PEAK_GBS * 1e9),
@@ -127,6 +163,52 @@ def run_dtype(sv, torch, dtype, n, steps, warmup, flags):
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+GOLDEN_30Q = os.path.join(ROOT, "tests", "golden", "layers30_qft30.npz")
+
+
+def precision_errors(sv, torch, n, flags):
+    """The error statement of each result of the step (outside the timed
+    region): for both circuits, the complex64 state against the complex128
+    state of the same circuit, compared on the device in FP64 (sv_compare:
+    max-abs amplitude error, relative 2-norm error, norm drift); and at 30
+    qubits both states against the oracle's complex128 amplitudes at the
+    sampled indices of the committed fixture."""
+    x, qft, layers = workload(n)
+    gold = None
+    if n == 30 and os.path.exists(GOLDEN_30Q):
+        with np.load(GOLDEN_30Q) as z:
+            gold = {k: z[k] for k in z.files}
+    out = {}
+    for name, g, x0 in (("qft", qft, x), ("layers", layers, 0)):
+        a = sv.StateVector(n, sv.SV_C64, basis_index=x0)
+        b = sv.StateVector(n, sv.SV_C128, basis_index=x0)
+        try:
+            a.run(g, flags)
+            b.run(g, flags)
+            c = sv.sv_compare(a.handle, b.handle)
+            res = {"gates": int(len(g)), "c64_vs_c128_max_abs": c["max_abs"],
+                   "c64_vs_c128_rel_l2": c["rel_l2"], "c64_norm_drift": c["norm_drift"],
+                   "c128_norm_drift": abs(c["norm_b"] - 1.0),
+                   "c64_rel_l2_bound": 8.0 * len(g) ** 0.5 * 2.0 ** -24}
+            if gold is not None:
+                idx = torch.from_numpy(gold["indices"]).to(a.tensor.device)
+                ref = gold[f"{name}_amp"]
+                g64 = a.tensor[idx].cpu().numpy().astype(np.complex128)
+                g128 = b.tensor[idx].cpu().numpy()
+                res["vs_oracle_sampled"] = {
+                    "indices": int(len(ref)),
+                    "c128_max_abs": float(np.max(np.abs(g128 - ref))),
+                    "c64_max_abs": float(np.max(np.abs(g64 - ref))),
+                    "c64_rel_l2": float(np.linalg.norm(g64 - ref) / np.linalg.norm(ref))}
+        finally:
+            a.close()
+            b.close()
+            torch.cuda.empty_cache()
+        out[name] = res
+        log(f"[bench] {name}: c64 vs c128 max-abs {c['max_abs']:.3e} rel {c['rel_l2']:.3e}")
+    return out
+
+
 KERNEL_SOURCE = {"tile": "kernels_tile.hip", "pair": "kernels_gate.hip",
                  "pair_ctrl": "kernels_gate.hip", "swap": "kernels_gate.hip",
                  "diag": "kernels_gate.hip", "dense": "kernels_dense.hip"}
@@ -154,15 +236,24 @@ def measured_traffic(cls, dtype_tag):
     return None
 
 
-def roofline(prof, dtype_tag):
+def roofline(run, dtype_tag):
     """Roofline of the kernel class with the most device time. Its bound is
     the roof with the longer ideal time per launch at the published peaks:
     HBM (algorithmic bytes / 8 TB/s) or vector ALU (algorithmic flops / the
-    dtype's vector peak); the other roof is given as `secondary`."""
+    dtype's vector peak); the other roof is given as `secondary`.
+
+    Algorithmic flops of the tile passes are the method's own, gate by gate
+    (method_flops: every gate of a step is applied inside some tile pass, so a
+    pass is credited the step's flops divided by its passes per step); the
+    flops of the fused ops the passes execute are reported beside them."""
+    prof = run["profile"]
     cls, d = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = d["total_ms"] / d["launches"]
     per_launch = d["bytes"] / d["launches"]
-    flops = d["flops"] / d["launches"]
+    op_flops = d["flops"] / d["launches"]
+    flops = op_flops
+    if cls == "tile":
+        flops = run["method_flops_per_step"] * run["steps"] / d["launches"]
     mfma = cls == "dense"
     alu_peak = (MFMA_PEAK_TFLOPS if mfma else ALU_PEAK_TFLOPS)[dtype_tag]
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
@@ -178,6 +269,8 @@ def roofline(prof, dtype_tag):
     out.update({"traffic": measured_traffic(cls, dtype_tag), "kernel": cls,
                 "launches": d["launches"], "avg_ms": round(avg_ms, 4),
                 "bytes_per_launch": per_launch, "flops_per_launch": flops,
+                "flops_per_launch_fused_ops": op_flops,
+                "flops_counted": "method, gate by gate" if cls == "tile" else "kernel ops",
                 "secondary": second})
     return out
 
@@ -190,7 +283,7 @@ def run_batched(sv, torch, count, seed=3):
     from paper_1801_01037_amd import autotune
     specs = qc.batch_specs(seed, count, 10, 24, 20, 200)
     stream = torch.cuda.Stream()
-    states, plans, gates = [], [], 0
+    states, plans, gates, alg_bytes = [], [], 0, 0.0
     t0 = time.perf_counter()
     for n, d, gs in specs:
         g = qc.layer_circuit(n, d, gs)
@@ -198,6 +291,8 @@ def run_batched(sv, torch, count, seed=3):
         st = sv.StateVector(n, sv.SV_C64, stream=stream)
         states.append(st)
         plans.append(sv.sv_plan_create(st.handle, g))
+        # algorithmic bytes of the circuit: every pass reads and writes the state
+        alg_bytes += sv.sv_plan_passes(plans[-1]) * 2 * 8 * 2.0 ** n
     plan_s = time.perf_counter() - t0
     tune_n = min(64, count)
     (bpc, tpt), tune_times = autotune.tune_batch(sv.SV_C64, plans[:tune_n], f"layers-{tune_n}",
@@ -258,6 +353,10 @@ def run_batched(sv, torch, count, seed=3):
             "p50_ms": round(float(np.percentile(end, 50)), 3),
             "p99_ms": round(float(np.percentile(end, 99)), 3),
             "makespan_ms": round(float(end.max()), 3), "wall_ms": round(wall * 1e3, 3),
+            "effective_GBps": round(alg_bytes / (float(end.max()) * 1e-3) / 1e9, 1),
+            "effective_GBps_note": "algorithmic bytes (2 N s per tile pass) over the makespan; "
+                                   "states of n <= 24 complex64 fit the 256 MiB last-level cache, "
+                                   "so this is not a fraction of HBM bandwidth",
             "gates_per_s": round(gates / wall, 1), "circuits_per_s": round(count / wall, 2),
             "autotuned": {"blocks_per_cu": bpc, "tiles_per_task": tpt,
                           "candidates_ms": {k: round(v, 3) for k, v in tune_times.items()}},
@@ -391,6 +490,28 @@ def run_xl(sv, torch, reps=1):
             st.close()
             torch.cuda.empty_cache()
         out[tag] = res
+    # Side by side at 33 qubits: the complex64 state (64 GiB) against the
+    # complex128 state (128 GiB) of the same circuit, compared on the device.
+    n = 33
+    g = qc.layer_circuit(n, 10, 1000 + n)
+    a = sv.StateVector(n, sv.SV_C64)
+    b = sv.StateVector(n, sv.SV_C128)
+    try:
+        res = {"gates": int(len(g)), "c64_rel_l2_bound": 8.0 * len(g) ** 0.5 * 2.0 ** -24}
+        for name, flags in (("fused", sv.SV_FUSE), ("dense", sv.SV_FUSE_DENSE)):
+            a.reset(0)
+            b.reset(0)
+            a.run(g, flags)
+            b.run(g, flags)
+            c = sv.sv_compare(a.handle, b.handle)
+            res[name] = {"max_abs": c["max_abs"], "rel_l2": c["rel_l2"],
+                         "c64_norm_drift": c["norm_drift"], "c128_norm_drift": abs(c["norm_b"] - 1.0)}
+            log(f"[bench] xl 33q c64 vs c128 {name}: max-abs {c['max_abs']:.2e} rel {c['rel_l2']:.2e}")
+    finally:
+        a.close()
+        b.close()
+        torch.cuda.empty_cache()
+    out["c64_vs_c128_33q"] = res
     return out
 
 
@@ -408,23 +529,83 @@ def run_serving(arrivals, rate=100.0, seed=0):
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
 
 
-def cpu_baseline(n, budget_s):
-    """The oracle stepping the same 30-qubit layered circuit, gate by gate, on one
-    host thread, until `budget_s` seconds have been spent (at least 2 gates)."""
-    import oracle
-    _, _, layers = workload(n)
+def host_cpu():
+    """Threads this process may run on and the host's CPU model."""
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return int(threads or 1), model
+
+
+def _oracle_gates_per_s(oracle, n, gates, budget_s):
+    """Whole gates of `gates`, in order from |0>, until budget_s has passed
+    (at least 2); returns (gates done, seconds)."""
     psi = oracle.basis_state(n, 0)
     done, t0 = 0, time.perf_counter()
-    while done < len(layers):
-        oracle.run_circuit(psi, layers[done:done + 1])
+    while done < len(gates):
+        oracle.run_circuit(psi, gates[done:done + 1])
         done += 1
         if done >= 2 and time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
     del psi
-    return {"value": round(done / el, 5), "unit": "gates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} gates of the {n}-qubit depth-20 layered circuit "
-                      f"(complex128, from |0>), {el:.1f} s on one host thread"}
+    return done, el
+
+
+def cpu_baseline(n, budget_s):
+    """The oracle stepping the same 30-qubit layered circuit, whole gates in
+    order, on every host thread this process may use (the OpenMP build, the
+    same bits as the reference build) and on one thread (the reference
+    build), each for half of `budget_s`."""
+    import oracle
+    _, _, layers = workload(n)
+    threads, model = host_cpu()
+    used = oracle.set_threads(threads)
+    d_all, t_all = _oracle_gates_per_s(oracle, n, layers, budget_s / 2)
+    oracle.set_threads(1)
+    d_one, t_one = _oracle_gates_per_s(oracle, n, layers, budget_s / 2)
+    return {"value": round(d_all / t_all, 5), "unit": "gates/s", "cores": used, "kind": "oracle",
+            "sample": f"first {d_all} gates of the {n}-qubit depth-20 layered circuit "
+                      f"(complex128, from |0>), {t_all:.1f} s on {used} host threads",
+            "single_thread": {"value": round(d_one / t_one, 5), "cores": 1,
+                              "sample": f"first {d_one} gates, {t_one:.1f} s on one host thread"},
+            "host": {"threads_available": threads, "cpu_model": model}}
+
+
+def run_cpu_sweep(ns=(16, 20, 24, 28, 30), min_s=1.0):
+    """The oracle's per-gate cost as the paper times single gates: a Haar 2x2
+    gate on qubit 0, the middle qubit and the last one, at each n, on one
+    host thread and on every available thread; each figure is the mean over
+    repeats that fill at least `min_s` seconds (at least one)."""
+    import oracle
+    import qcircuits as qc
+    threads, model = host_cpu()
+    u = qc.haar_su2(5, 1)[0]
+    rows = []
+    for n in ns:
+        psi = oracle.basis_state(n, 0)
+        for k in (1, threads):
+            used = oracle.set_threads(k)
+            for q in (0, n // 2, n - 1):
+                g = qc.gate_u(q, u)
+                reps, t0 = 0, time.perf_counter()
+                while reps < 1 or time.perf_counter() - t0 < min_s:
+                    oracle.run_circuit(psi, g)
+                    reps += 1
+                sec = (time.perf_counter() - t0) / reps
+                rows.append({"n": n, "target": q, "threads": used, "s_per_gate": sec,
+                             "GBps": round(2 * 16 * 2.0 ** n / sec / 1e9, 2)})
+                log(f"[bench] cpu n={n} q={q} threads={used}: {sec * 1e3:.2f} ms/gate")
+        oracle.set_threads(1)
+        del psi
+    return {"host": {"threads_available": threads, "cpu_model": model}, "rows": rows}
 
 
 def main():
@@ -434,6 +615,19 @@ def main():
         log("bench.py measures one GPU only: this build has no multi-GPU path "
             f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).")
         sys.exit(2)
+    if args.mode == "cpu_sweep":
+        extra = run_cpu_sweep()
+        rows = [r for r in extra["rows"] if r["n"] == 30 and r["threads"] > 1]
+        value = round(1.0 / float(np.mean([r["s_per_gate"] for r in rows])), 4) if rows else None
+        print(json.dumps({"metric": "30q gates/s and % HBM peak, c64 vs c128; batched p50/p99 circuit latency",
+                          "value": value, "unit": "gates/s", "n_gpus": 0, "steps": 1, "warmup": 0,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "oracle per-gate cost: Haar 2x2 on qubits 0, n/2, "
+                                                 "n-1 at n = 16..30, one and all host threads",
+                                     "mode": args.mode},
+                          "cpu_sweep": extra}))
+        return
     import torch
     import paper_1801_01037_amd as sv
     if not os.path.exists(sv.LIB_PATH):
@@ -480,7 +674,10 @@ def main():
                    "ms_per_step": round(r64["ms_per_step"], 3),
                    "effective_hbm_frac": round(r64["effective_hbm_frac"], 4),
                    "speedup_vs_c128": round(r64["gates_per_s"] / r128["gates_per_s"], 3),
-                   "roofline": roofline(r64["profile"], "c64"), "norm": r64["norm"]}
+                   "roofline": roofline(r64, "c64"), "norm": r64["norm"]}
+        if not args.no_errors:
+            log("[bench] error statement: complex64 against complex128 and the oracle")
+            out_c64["errors"] = precision_errors(sv, torch, n, flags)
     pergate = None
     if not args.no_pergate and args.mode == "fused":
         log("[bench] per-gate 1q passes")
@@ -523,7 +720,7 @@ def main():
                    "n_qubits": n, "gates_per_step": r128["gates_per_step"],
                    "mode": args.mode, "parallelism": "single GPU"},
         "effective_hbm_frac": round(r128["effective_hbm_frac"], 4),
-        "roofline": roofline(r128["profile"], "c128"),
+        "roofline": roofline(r128, "c128"),
         "cpu_baseline": cpu,
         "c64": out_c64,
         "pergate_1q": pergate,

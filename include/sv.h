@@ -212,6 +212,21 @@ sv_status sv_norm(sv_state s, double *out);
  * waiting. */
 sv_status sv_norm_device(sv_state s, double *out_dev);
 
+/* The error of state a against state b on the GPU, in FP64 (the error
+ * statement of a complex64 result against complex128: its largest amplitude
+ * error and its norm, the normalisation of section Quantum Information
+ * Processing): out[0] = max_i |a_i - b_i| (complex modulus), out[1] =
+ * sum_i |a_i - b_i|^2, out[2] = sum_i |a_i|^2, out[3] = sum_i |b_i|^2.
+ * Either state may be complex64 or complex128: amplitudes are widened to FP64
+ * before they are subtracted. The relative 2-norm error is
+ * sqrt(out[1] / out[3]) and a's norm drift |out[2] - 1|. Both states must
+ * have the same qubit count and device (SV_EINVAL otherwise). The comparison
+ * is queued on a's stream after the work queued so far on b's stream; the call
+ * waits for it (synchronous) and allocates 4100 doubles of device scratch for
+ * its duration. Both states are read once; the sums use a fixed reduction
+ * tree (the same bits on every call). */
+sv_status sv_compare(sv_state a, sv_state b, double out[4]);
+
 /* Copies the whole state (2^n amplitudes in the layout above) to / from host
  * memory. Synchronous. */
 sv_status sv_copy_out(sv_state s, void *host_dst);

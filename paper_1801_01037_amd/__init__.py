@@ -20,7 +20,7 @@ __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
     "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
-    "sv_run_circuit", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device",
+    "sv_run_circuit", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device", "sv_compare",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
     "sv_plan_passes", "sv_run_plan", "sv_batch_create", "sv_batch_destroy", "sv_batch_config",
@@ -85,6 +85,7 @@ _SIGNATURES = {
     "sv_probs_device": ([_vp, _u64, _u64, _vp], _int),
     "sv_norm": ([_vp, _dp], _int),
     "sv_norm_device": ([_vp, _vp], _int),
+    "sv_compare": ([_vp, _vp, _dp], _int),
     "sv_copy_out": ([_vp, _vp], _int),
     "sv_copy_in": ([_vp, _vp], _int),
     "sv_synchronize": ([_vp], _int),
@@ -264,6 +265,18 @@ def sv_norm(h: int) -> float:
 
 def sv_norm_device(h: int, out_dev: int) -> None:
     _check(lib().sv_norm_device(h, out_dev))
+
+
+def sv_compare(a: int, b: int) -> dict:
+    """State a against state b in FP64 on the GPU: max-abs amplitude error,
+    sum |a - b|^2, both norms, and the derived relative 2-norm error and a's
+    norm drift (see include/sv.h)."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(lib().sv_compare(a, b, out.ctypes.data_as(_dp)))
+    mx, d2, na, nb = (float(v) for v in out)
+    return {"max_abs": mx, "sq_err": d2, "norm_a": na, "norm_b": nb,
+            "rel_l2": (d2 / nb) ** 0.5 if nb > 0 else float("nan"),
+            "norm_drift": abs(na - 1.0)}
 
 
 def sv_copy_out(h: int) -> np.ndarray:

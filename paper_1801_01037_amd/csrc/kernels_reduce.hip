@@ -78,6 +78,84 @@ __global__ __launch_bounds__(kNormBlocks) void k_norm_final(const double *partia
     if (threadIdx.x == 0) *out = s;
 }
 
+// Two amplitudes (2p, 2p + 1) of a state, widened to FP64.
+template <bool C64, bool NT>
+__device__ __forceinline__ void load_pair(const void *psi, uint64_t p, double (&v)[4])
+{
+    if constexpr (C64) {
+        const float4 a = ld16<NT>(static_cast<const float4 *>(psi) + p);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+        const double2 *q = static_cast<const double2 *>(psi) + 2 * p;
+        const double2 a = ld16<NT>(q), b = ld16<NT>(q + 1);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// The four comparison figures of one thread, reduced over the block: thread
+// k < 4 writes figure k to out[k * stride]. Figures: 0 the largest
+// |a_i - b_i|^2, 1 sum |a_i - b_i|^2, 2 sum |a_i|^2, 3 sum |b_i|^2.
+template <int kThreads>
+__device__ __forceinline__ void block_compare(double (&r)[4], double *out, uint32_t stride)
+{
+    __shared__ double w[4][kThreads / 64];
+    r[0] = wave_max(r[0]);
+    for (int k = 1; k < 4; ++k) r[k] = wave_sum(r[k]);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) w[k][wave] = r[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double s = w[k][0];
+        for (int i = 1; i < kThreads / 64; ++i) s = k == 0 ? fmax(s, w[k][i]) : s + w[k][i];
+        out[k * stride] = s;
+    }
+}
+
+// The error of state a against state b (same length, either precision), all
+// in FP64: a fixed-shape reduction like the norm's (the same bits every call).
+// Block b's figures go to part[k * kNormBlocks + b].
+template <bool AC64, bool BC64, bool NT>
+__global__ __launch_bounds__(kBlock) void k_compare_partial(const void *a, const void *b,
+                                                            uint64_t pairs, double *part)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    uint64_t p = uint64_t(xcd_block(blockIdx.x, gridDim.x % 8 == 0 ? gridDim.x / 8 : 0)) * kBlock +
+                 threadIdx.x;
+    for (; p < pairs; p += stride) {
+        double x[4], y[4];
+        load_pair<AC64, NT>(a, p, x);
+        load_pair<BC64, NT>(b, p, y);
+        for (int h = 0; h < 4; h += 2) {
+            const double dr = x[h] - y[h], di = x[h + 1] - y[h + 1];
+            const double d2 = dr * dr + di * di;
+            r[0] = fmax(r[0], d2);
+            r[1] += d2;
+            r[2] += x[h] * x[h] + x[h + 1] * x[h + 1];
+            r[3] += y[h] * y[h] + y[h + 1] * y[h + 1];
+        }
+    }
+    block_compare<kBlock>(r, part + blockIdx.x, kNormBlocks);
+}
+
+// out[0] = max |a_i - b_i|, out[1..3] the three sums.
+__global__ __launch_bounds__(kNormBlocks) void k_compare_final(const double *part, double *out)
+{
+    double r[4];
+    for (int k = 0; k < 4; ++k) r[k] = part[k * kNormBlocks + threadIdx.x];
+    block_compare<kNormBlocks>(r, out, 1);
+    if (threadIdx.x == 0) out[0] = sqrt(out[0]);   // thread 0 wrote out[0] itself
+}
+
 template <bool C64>
 __global__ __launch_bounds__(kBlock) void k_probs(const void *psi, uint64_t first,
                                                   uint64_t count, double *out)
@@ -108,6 +186,35 @@ hipError_t launch_norm(const void *psi, int n, sv_dtype dt, double *partials, do
         else hipLaunchKernelGGL((k_norm_partial<false, false>), grid, block, 0, st, psi, chunks, partials);
     }
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormBlocks), 0, st, partials, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare(const void *a, sv_dtype da, const void *b, sv_dtype db, int n,
+                          double *scratch, hipStream_t st)
+{
+    const uint64_t pairs = uint64_t(1) << (n - 1);
+    const uint64_t bytes = (uint64_t(1) << n) * uint64_t(elem_bytes(da) + elem_bytes(db));
+    const bool nt = bytes > kStreamBytes;
+    const dim3 grid(kNormBlocks), block(kBlock);
+#define SV_CMP(A, B)                                                                            \
+    do {                                                                                      \
+        if (nt) hipLaunchKernelGGL((k_compare_partial<A, B, true>), grid, block, 0, st, a, b,  \
+                                   pairs, scratch);                                           \
+        else hipLaunchKernelGGL((k_compare_partial<A, B, false>), grid, block, 0, st, a, b,    \
+                                pairs, scratch);                                              \
+    } while (0)
+    if (da == SV_C64) {
+        if (db == SV_C64) SV_CMP(true, true);
+        else SV_CMP(true, false);
+    } else {
+        if (db == SV_C64) SV_CMP(false, true);
+        else SV_CMP(false, false);
+    }
+#undef SV_CMP
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compare_final, dim3(1), dim3(kNormBlocks), 0, st, scratch,
+                       scratch + 4 * kNormBlocks);
     return hipGetLastError();
 }
 

@@ -585,6 +585,40 @@ sv_status sv_norm(sv_state s, double *out)
     return SV_OK;
 }
 
+sv_status sv_compare(sv_state a, sv_state b, double out[4])
+{
+    if (sv_status st = check_handle(a)) return st;
+    if (sv_status st = check_handle(b)) return st;
+    if (!out) return fail(SV_EINVAL, "null output pointer");
+    if (a->n != b->n) return fail(SV_EINVAL, "qubit counts differ (%d and %d)", a->n, b->n);
+    if (a->device != b->device)
+        return fail(SV_EINVAL, "states live on different devices (%d and %d)", a->device, b->device);
+    DeviceScope ds(a->device);
+    double *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, svk::kCompareScratch * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ENOMEM, "hipMalloc of comparison scratch failed: %s", hipGetErrorString(e));
+    }
+    // The comparison runs on a's stream after the work queued so far on b's.
+    hipEvent_t ev = nullptr;
+    if (a->stream != b->stream) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, b->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(a->stream, ev, 0);
+    }
+    if (e == hipSuccess)
+        e = svk::launch_compare(a->psi, a->dt, b->psi, b->dt, a->n, buf, a->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, buf + 4 * svk::kNormBlocks, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, a->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "state comparison");
+    return SV_OK;
+}
+
 sv_status sv_copy_out(sv_state s, void *host_dst)
 {
     if (sv_status st = check_handle(s)) return st;

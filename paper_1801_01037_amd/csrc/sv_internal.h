@@ -98,6 +98,12 @@ hipError_t launch_norm(const void *psi, int n, sv_dtype dt, double *partials,
                        double *out_dev, hipStream_t st);
 hipError_t launch_probs(const void *psi, sv_dtype dt, uint64_t first, uint64_t count,
                         double *out_dev, hipStream_t st);
+// States a and b of n qubits (n >= 1), each of either dtype, compared in FP64.
+// scratch: 4 * kNormBlocks + 4 doubles; the last four receive max |a_i - b_i|,
+// sum |a_i - b_i|^2, sum |a_i|^2 and sum |b_i|^2.
+constexpr int kCompareScratch = 4 * kNormBlocks + 4;
+hipError_t launch_compare(const void *a, sv_dtype da, const void *b, sv_dtype db, int n,
+                          double *scratch, hipStream_t st);
 
 // ---- host helpers (sv_api.hip) ---------------------------------------------
 // Records `msg` as the calling thread's last error and returns `st`.
@@ -135,10 +141,9 @@ constexpr int kSampleBlockLog = 12;                 // amplitudes per block: 409
 constexpr int kSampleBlock = 1 << kSampleBlockLog;
 // Doubles of scratch sampling needs: the block sums, their exclusive prefix
 // with the norm at its end, and the index of the last non-zero block.
-inline uint64_t sample_scratch_doubles(int n)
+constexpr uint64_t sample_scratch_doubles(int n)
 {
-    const uint64_t nb = n < kSampleBlockLog ? 1 : (uint64_t(1) << (n - kSampleBlockLog));
-    return 2 * nb + 2;
+    return 2 * (n < kSampleBlockLog ? uint64_t(1) : (uint64_t(1) << (n - kSampleBlockLog))) + 2;
 }
 // S: sample_scratch_doubles(n) doubles of device scratch.
 hipError_t launch_block_sums(const void *psi, int n, sv_dtype dt, double *S, hipStream_t st);

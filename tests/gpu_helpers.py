@@ -1,5 +1,7 @@
 """Shared helpers of the GPU tests: tolerances and state transfer."""
+import contextlib
 import math
+import os
 
 import numpy as np
 
@@ -48,3 +50,23 @@ def rounded(host: np.ndarray, dtype: int) -> np.ndarray:
 
 DTYPES = [sv.SV_C128, sv.SV_C64]
 DTYPE_IDS = ["c128", "c64"]
+
+
+@contextlib.contextmanager
+def oracle_threads(k: int = 0):
+    """Runs the oracle on k host threads (default: the host's cores, at most
+    16) for the block, then back on one. The threaded build gives the same
+    bits as the single-threaded one (pinned in tests/test_oracle.py)."""
+    import oracle
+    used = oracle.set_threads(k or min(16, os.cpu_count() or 1))
+    try:
+        yield used
+    finally:
+        oracle.set_threads(1)
+
+
+# Sizes at which a state is larger than the last-level cache (streamed with the
+# nontemporal hint) and each tile pass has more tiles than resident
+# work-groups: (n, dtype) with 512 MiB states.
+STREAMING = [(25, sv.SV_C128), (26, sv.SV_C64)]
+STREAMING_IDS = ["25-c128", "26-c64"]

@@ -214,10 +214,10 @@ def test_expired_waits_are_reported_and_the_launch_ends():
 @pytest.mark.parametrize("flags", [0, sv.SV_GRAPH], ids=["launches", "graph"])
 @pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
 def test_persistent_batch_equals_alone(dtype, flags, max_tiles):
-    """Circuits small enough run whole in one persistent launch (the rest in
-    levels after it); every result equals the circuit run alone, bit for bit,
-    also on a graph replay (the queue counter is cleared by a kernel in the
-    graph), and every circuit's clock interval is filled."""
+    """Circuits small enough run whole in one persistent launch on the batch's
+    second stream (work-group w takes circuits w, w + G, ...), the rest in level
+    launches beside it; every result equals the circuit run alone, bit for bit,
+    also on a graph replay, and every circuit's clock interval is filled."""
     specs = _specs(20, 21, 4, 17, 5, 60)
     circuits = [qc.layer_circuit(n, d, s) for n, d, s in specs]
     states = [sv.sv_create(n, dtype) for n, _, _ in specs]

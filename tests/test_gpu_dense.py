@@ -7,7 +7,7 @@ import oracle
 import paper_1801_01037_amd as sv
 import qcircuits as qc
 from tests.gpu_helpers import C128_MAX_ABS, DTYPE_IDS, DTYPES, assert_close, c64_rel_tol
-from tests.gpu_helpers import rounded, state_from_host
+from tests.gpu_helpers import STREAMING, STREAMING_IDS, oracle_threads, rounded, state_from_host
 from tests.test_plan import mixed_circuit
 
 pytestmark = pytest.mark.gpu
@@ -20,6 +20,25 @@ def test_mixed_circuit_dense(dtype, n):
     psi0 = rounded(qc.random_state(n, 700 + n), dtype)
     ref = psi0.copy()
     oracle.run_circuit(ref, g)
+    h = state_from_host(n, dtype, psi0)
+    try:
+        sv.sv_run_circuit(h, g, sv.SV_FUSE_DENSE)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+    assert_close(got, ref, dtype, len(g), f"dense mixed n={n}")
+
+
+@pytest.mark.parametrize("n,dtype", STREAMING, ids=STREAMING_IDS)
+def test_mixed_circuit_dense_streaming_sizes(n, dtype):
+    """Dense blocks on states past the last-level cache (blocks with no qubit
+    inside a 128-byte line stream with the nontemporal hint), against the
+    oracle element by element."""
+    g = mixed_circuit(n, 300, 11 * n + 3)
+    psi0 = rounded(qc.random_state(n, 700 + n), dtype)
+    ref = psi0.copy()
+    with oracle_threads():
+        oracle.run_circuit(ref, g)
     h = state_from_host(n, dtype, psi0)
     try:
         sv.sv_run_circuit(h, g, sv.SV_FUSE_DENSE)

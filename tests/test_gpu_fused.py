@@ -11,7 +11,8 @@ import pytest
 import oracle
 import paper_1801_01037_amd as sv
 import qcircuits as qc
-from tests.gpu_helpers import DTYPE_IDS, DTYPES, assert_close, rounded, state_from_host
+from tests.gpu_helpers import DTYPE_IDS, DTYPES, STREAMING, STREAMING_IDS, assert_close
+from tests.gpu_helpers import oracle_threads, rounded, state_from_host
 from tests.test_plan import mixed_circuit
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +32,42 @@ def test_mixed_circuit_fused(dtype, n):
     finally:
         sv.sv_destroy(h)
     assert_close(got, ref, dtype, len(g), f"fused mixed n={n}")
+
+
+@pytest.mark.parametrize("n,dtype", STREAMING, ids=STREAMING_IDS)
+def test_mixed_circuit_fused_streaming_sizes(n, dtype):
+    """States past the last-level cache (tile loads and stores with the
+    nontemporal hint) and many tiles per work-group (LDS slots reused from
+    tile to tile), element by element against the oracle."""
+    g = mixed_circuit(n, 400, 7 * n + 1)
+    psi0 = rounded(qc.random_state(n, 300 + n), dtype)
+    ref = psi0.copy()
+    with oracle_threads():
+        oracle.run_circuit(ref, g)
+    h = state_from_host(n, dtype, psi0)
+    try:
+        sv.sv_run_circuit(h, g, sv.SV_FUSE)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+    assert_close(got, ref, dtype, len(g), f"fused mixed n={n}")
+
+
+@pytest.mark.parametrize("n,dtype", STREAMING, ids=STREAMING_IDS)
+def test_layers_qft_fused_streaming_sizes(n, dtype):
+    """The benchmark's circuit kinds (layers, then the QFT) at streaming sizes."""
+    g = np.concatenate([qc.layer_circuit(n, 6, n), qc.qft_circuit(n)])
+    x = qc.random_basis_index(n, 3)
+    with oracle_threads():
+        ref = oracle.simulate(n, g, x)
+    h = sv.sv_create(n, dtype)
+    try:
+        sv.sv_reset(h, x)
+        sv.sv_run_circuit(h, g, sv.SV_FUSE)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+    assert_close(got, ref, dtype, len(g), f"layers+qft fused n={n}")
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)

@@ -15,7 +15,8 @@ import pytest
 import oracle
 import paper_1801_01037_amd as sv
 import qcircuits as qc
-from tests.gpu_helpers import DTYPE_IDS, DTYPES, assert_close, rounded, state_from_host
+from tests.gpu_helpers import DTYPE_IDS, DTYPES, assert_close, oracle_threads, rounded
+from tests.gpu_helpers import state_from_host
 from tests.test_plan import mixed_circuit
 
 pytestmark = pytest.mark.gpu
@@ -47,6 +48,12 @@ CASES = [
     ("mixed", 19, lambda n: mixed_circuit(n, 1500, 5 * n + 4), C128),
     ("qft+layers", 20, lambda n: np.concatenate([qc.qft_circuit(n), qc.layer_circuit(n, 20, 3)]), C128),
     ("qft+layers", 20, lambda n: np.concatenate([qc.qft_circuit(n), qc.layer_circuit(n, 20, 3)]), C64),
+    # states past the last-level cache, many tiles per work-group
+    ("layers", 25, lambda n: qc.layer_circuit(n, 12, n * 100 + 12), C128),
+    ("layers", 26, lambda n: qc.layer_circuit(n, 12, n * 100 + 12), C64),
+    ("mixed", 25, lambda n: mixed_circuit(n, 1000, 5 * n + 4), C128),
+    ("mixed", 26, lambda n: mixed_circuit(n, 1500, 5 * n + 4), C64),
+    ("qft+layers", 25, lambda n: np.concatenate([qc.qft_circuit(n), qc.layer_circuit(n, 10, 3)]), C128),
 ]
 
 
@@ -60,7 +67,8 @@ def test_relabelled_passes_match_oracle(kind, n, make, dtype):
     assert moved < fixed, "relabelling does not change this plan"
     psi0 = rounded(qc.random_state(n, 900 + n), dtype)
     ref = psi0.copy()
-    oracle.run_circuit(ref, g)
+    with oracle_threads():
+        oracle.run_circuit(ref, g)
     got = _run(n, dtype, psi0, g, sv.SV_FUSE)
     assert_close(got, ref, dtype, len(g), f"{kind} n={n} relabelled")
     base = _run(n, dtype, psi0, g, sv.SV_FUSE | sv.SV_NO_RELABEL)
