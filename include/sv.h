@@ -249,6 +249,20 @@ sv_status sv_synchronize(sv_state s);
  * amplitudes that receive samples. */
 sv_status sv_sample_device(sv_state s, const double *u_dev, uint64_t count, uint64_t *out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * draws as sv_sample_device, bit for bit, with no allocation of any kind. Its
+ * scratch (block sums and their prefix) is a static device array of
+ * 2^19 + 2 doubles (4 MiB) that each GPU the library runs on holds until the
+ * process ends; so n must be at most 30 (SV_EINVAL above, with nothing
+ * queued). Every call on one GPU shares that array: calls queued on one
+ * stream are ordered, but calls that overlap on one GPU (other streams or
+ * threads) race and give unspecified draws. Nothing in the array needs to be
+ * cleared between calls (each call writes every entry it reads). Arguments,
+ * errors and the queueing on the handle's stream are as in sv_sample_device. */
+sv_status sv_sample_device_noalloc(sv_state s, const double *u_dev, uint64_t count,
+                                   uint64_t *out_dev);
+
 /* ---- planned circuits and batched launches --------------------------------
  * A plan is a circuit fused into tile passes (as SV_FUSE does) and uploaded to
  * the device once; it stays bound to the state it was made for. A batch runs

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
-    "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
+    "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_sample_device_noalloc", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
     "sv_run_circuit", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device", "sv_compare",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
     "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
@@ -78,6 +78,7 @@ _SIGNATURES = {
     "sv_apply_unitary": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _dp], _int),
     "sv_reset_uniform": ([_vp], _int),
     "sv_sample_device": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
+    "sv_sample_device_noalloc": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
     "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
     "sv_run_batch": ([_vp, _vp, _vp, _sz, _u32], _int),
@@ -191,6 +192,12 @@ def sv_sample_device(h: int, u_dev: int, count: int, out_dev: int) -> None:
     """Device pointers: `count` ascending doubles in [0, 1) in, `count` uint64
     indices out (see include/sv.h)."""
     _check(lib().sv_sample_device(h, u_dev, count, out_dev))
+
+
+def sv_sample_device_noalloc(h: int, u_dev: int, count: int, out_dev: int) -> None:
+    """As sv_sample_device, with the library's static scratch (n <= 30; no
+    allocation of any kind)."""
+    _check(lib().sv_sample_device_noalloc(h, u_dev, count, out_dev))
 
 
 def sv_apply_1q(h: int, target: int, m) -> None:

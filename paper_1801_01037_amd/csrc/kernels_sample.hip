@@ -13,9 +13,17 @@
 //
 // The uniform state 2^{-n/2} sum_x |x> (H on every qubit of |0...0>, section
 // Quantum Information Processing) is one write of the state.
+#include <mutex>
 #include <type_traits>
 
 #include "sv_internal.h"
+
+// Sampling scratch for callers that cannot allocate device memory: block sums
+// and their prefix for states of up to kStaticSampleMaxQubits qubits (4 MiB).
+// Each GPU holds its own copy until the process ends. In host code this name
+// stands for a host-side shadow, not a device address: host code passes the
+// address that static_sample_scratch looks up, never the name itself.
+static __device__ __align__(256) double scratch[svk::sample_scratch_doubles(svk::kStaticSampleMaxQubits)];
 
 namespace svk {
 namespace {
@@ -207,6 +215,24 @@ unsigned grid_of(uint64_t items, uint64_t cap)
 }
 
 }  // namespace
+
+hipError_t static_sample_scratch(int device, double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_block_sums(const void *psi, int n, sv_dtype dt, double *S, hipStream_t st)
 {

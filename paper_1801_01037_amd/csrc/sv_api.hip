@@ -736,4 +736,24 @@ sv_status sv_sample_device(sv_state s, const double *u_dev, uint64_t count, uint
     return SV_OK;
 }
 
+sv_status sv_sample_device_noalloc(sv_state s, const double *u_dev, uint64_t count,
+                                   uint64_t *out_dev)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (s->n > svk::kStaticSampleMaxQubits)
+        return fail(SV_EINVAL, "n = %d exceeds the %d qubits the static sampling scratch serves "
+                    "(sv_sample_device takes any n)", s->n, svk::kStaticSampleMaxQubits);
+    if (count == 0) return SV_OK;
+    if (!u_dev || !out_dev) return fail(SV_EINVAL, "null device pointer");
+    DeviceScope ds(s->device);
+    double *S = nullptr;
+    SV_HIP(svk::static_sample_scratch(s->device, &S), "static sampling scratch lookup");
+    // Every scratch entry the launches read is written by them first (block
+    // sums, then their prefix), so nothing is cleared between calls.
+    SV_HIP(svk::launch_block_sums(s->psi, s->n, s->dt, S, s->stream), "block-sum kernel launch");
+    SV_HIP(svk::launch_sample(s->psi, s->n, s->dt, S, u_dev, count, out_dev, s->stream),
+           "sampling kernel launch");
+    return SV_OK;
+}
+
 }  // extern "C"

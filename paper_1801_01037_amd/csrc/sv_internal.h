@@ -145,6 +145,12 @@ constexpr uint64_t sample_scratch_doubles(int n)
 {
     return 2 * (n < kSampleBlockLog ? uint64_t(1) : (uint64_t(1) << (n - kSampleBlockLog))) + 2;
 }
+// Largest state the static sampling scratch serves (sv_sample_device_noalloc).
+constexpr int kStaticSampleMaxQubits = 30;
+// The static sampling scratch of the current device: sample_scratch_doubles(
+// kStaticSampleMaxQubits) doubles, held until the process ends. Its device
+// address is looked up once per device (the device must be current).
+hipError_t static_sample_scratch(int device, double **out);
 // S: sample_scratch_doubles(n) doubles of device scratch.
 hipError_t launch_block_sums(const void *psi, int n, sv_dtype dt, double *S, hipStream_t st);
 // u: m ascending doubles in [0, 1) (device); out: m indices (device).
