@@ -48,13 +48,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl", "cpu_sweep"],
+    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl", "cpu_sweep",
+                                       "graph"],
                     default="fused",
                     help="fused: SV_FUSE tile passes; pergate: one launch per gate; "
                          "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores; "
                          "sweep: per-gate timings on every qubit at 30 qubits; "
                          "xl: the 33-qubit complex128 / 34-qubit complex64 depth-10 circuit; "
-                         "cpu_sweep: the oracle's per-gate cost on the host (no GPU)")
+                         "cpu_sweep: the oracle's per-gate cost on the host (no GPU); "
+                         "graph: host cost of short circuits with and without SV_GRAPH")
     ap.add_argument("--reps", type=int, default=20, help="timed repetitions per gate (sweep)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample")
@@ -515,6 +517,45 @@ def run_xl(sv, torch, reps=1):
     return out
 
 
+def run_graph_cost(sv, torch, reps=30):
+    """Short circuits run again and again, with and without SV_GRAPH: the host
+    time a call takes to return (planning and launches) and the time to its
+    completion, median over `reps` calls after warm-up; per-pass figures divide
+    by the tile passes of one call."""
+    import qcircuits as qc
+    out = {}
+    for n, depth, dt, tag in ((10, 20, sv.SV_C64, "c64"), (14, 20, sv.SV_C64, "c64"),
+                              (18, 20, sv.SV_C128, "c128"), (22, 10, sv.SV_C128, "c128")):
+        g = qc.layer_circuit(n, depth, 5)
+        passes = sv.sv_plan_inspect(n, dt, g, sv.SV_FUSE)[1]
+        st = sv.StateVector(n, dt)
+        res = {"gates": int(len(g)), "passes": int(passes)}
+        try:
+            for name, flags in (("direct", sv.SV_FUSE), ("graph", sv.SV_FUSE | sv.SV_GRAPH)):
+                for _ in range(3):
+                    st.run(g, flags)
+                st.synchronize()
+                host, done = [], []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    st.run(g, flags)
+                    t1 = time.perf_counter()
+                    st.synchronize()
+                    t2 = time.perf_counter()
+                    host.append(t1 - t0)
+                    done.append(t2 - t0)
+                h, d = float(np.median(host)) * 1e3, float(np.median(done)) * 1e3
+                res[name] = {"host_ms": round(h, 4), "completion_ms": round(d, 4),
+                             "host_us_per_pass": round(1e3 * h / max(passes, 1), 2)}
+            log(f"[bench] graph n={n} {tag}: host {res['direct']['host_ms']:.3f} -> "
+                f"{res['graph']['host_ms']:.3f} ms, done {res['direct']['completion_ms']:.3f} -> "
+                f"{res['graph']['completion_ms']:.3f} ms")
+        finally:
+            st.close()
+        out[f"n{n}_{tag}"] = res
+    return out
+
+
 def run_serving(arrivals, rate=100.0, seed=0):
     from paper_1801_01037_amd import serving
     reqs = serving.poisson_requests(rate, arrivals, seed)
@@ -643,9 +684,18 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
         del src, dst
-    if args.mode in ("sweep", "xl"):
-        extra = run_sweep(sv, torch, args.qubits, args.reps) if args.mode == "sweep" else run_xl(sv, torch)
+    if args.mode in ("sweep", "xl", "graph"):
         if args.mode == "sweep":
+            extra = run_sweep(sv, torch, args.qubits, args.reps)
+        elif args.mode == "xl":
+            extra = run_xl(sv, torch)
+        else:
+            extra = run_graph_cost(sv, torch)
+        if args.mode == "graph":
+            value = round(extra["n14_c64"]["gates"] / (extra["n14_c64"]["graph"]["completion_ms"] * 1e-3), 1)
+            workload = ("short layered circuits (n = 10, 14, 18, 22) run again and again with "
+                        "SV_FUSE, with and without SV_GRAPH: host time per call and completion")
+        elif args.mode == "sweep":
             value = extra["c128"]["one_qubit_gates_per_s"]
             workload = (f"{args.qubits}-qubit per-gate timings: Haar 2x2 on every qubit, CNOTs, "
                         "controlled phases, general 5-qubit gates; median of "

@@ -90,9 +90,10 @@ typedef struct {
                            /* the call's work completes                             */
 #define SV_FUSE_DENSE  2u  /* group gates into dense 2^k x 2^k blocks on k <= 5      */
                            /* qubits, multiplied on the matrix cores (MFMA)          */
-#define SV_GRAPH       4u  /* sv_batch_run only (see there): capture the level      */
-                           /* launches in a HIP graph and replay it. sv_run_circuit */
-                           /* rejects it with SV_EUNSUPPORTED                        */
+#define SV_GRAPH       4u  /* capture the call's launches in a HIP graph once and   */
+                           /* replay it when the same gate list (and flags) comes   */
+                           /* back (sv_run_circuit), or the same batch request      */
+                           /* (sv_batch_run, see there)                              */
 #define SV_NO_RELABEL  8u  /* with SV_FUSE: keep the standard storage order between */
                            /* passes (qubits 0..2, or 0..3 for complex64, in every  */
                            /* tile)                                                  */
@@ -173,9 +174,18 @@ sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
 
 /* Applies n_gates gates in order (the circuit of section Quantum Circuits).
  * The gate array is read during the call only. flags: 0, SV_FUSE (optionally
- * | SV_NO_RELABEL) or SV_FUSE_DENSE. Fusion reorders only gates that act on
- * disjoint qubits, so the result equals the in-order product up to rounding.
- * All gates are validated before any work is queued. */
+ * | SV_NO_RELABEL) or SV_FUSE_DENSE, each optionally | SV_GRAPH. Fusion
+ * reorders only gates that act on disjoint qubits, so the result equals the
+ * in-order product up to rounding. All gates are validated before any work is
+ * queued.
+ * SV_GRAPH: the first call plans the list, uploads what its kernels read into
+ * buffers of its own and captures the launches (no copies, no memsets) in a
+ * HIP graph held by the handle; a later call with the same gate list (compared
+ * byte for byte) and the same other flags replays that graph on the handle's
+ * stream, with no planning and one host launch. The results are bit for bit
+ * those of the same flags without SV_GRAPH. One graph is kept per handle: a
+ * different list or flags wait for the handle's earlier replays, free the old
+ * graph and capture anew. sv_destroy frees it. */
 sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags);
 
 /* Runs count independent circuits, circuits[c] (lens[c] gates) on states[c],

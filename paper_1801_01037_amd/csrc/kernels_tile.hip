@@ -12,6 +12,9 @@
 // which leaves the amplitudes the tile covers unchanged). LDS slots are padded by one
 // element every 256 bytes so that register gathers with large local strides
 // spread over the banks.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "sv_internal.h"
@@ -714,20 +717,46 @@ hipError_t set_max_lds(Kern kern, bool c64)
                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
+// Work-groups of `kern` that fit on one CU with `threads` threads and `lds`
+// bytes of LDS, after raising the kernel's LDS limit. Both are asked of the
+// runtime once per (kernel, device, shape) and then kept: a short circuit
+// queues many tile launches, and each query costs host time.
+template <typename Kern>
+hipError_t resident_per_cu(Kern kern, bool c64, int threads, size_t lds, int *per_cu)
+{
+    using Key = std::tuple<const void *, int, int, size_t>;
+    static std::mutex mu;
+    static std::map<Key, int> known;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const Key key{reinterpret_cast<const void *>(kern), dev, threads, lds};
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = known.find(key);
+    if (it != known.end()) {
+        *per_cu = it->second;
+        return hipSuccess;
+    }
+    hipError_t e = set_max_lds(kern, c64);
+    if (e != hipSuccess) return e;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, lds) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        n = 1;
+    }
+    known.emplace(key, n);
+    *per_cu = n;
+    return hipSuccess;
+}
+
 template <typename Kern>
 hipError_t launch_k(Kern kern, bool c64, const TileArgs &a, int K, size_t lds, hipStream_t st)
 {
-    hipError_t e = set_max_lds(kern, c64);
-    if (e != hipSuccess) return e;
     // One work-group per resident slot (LDS and registers decide how many
     // fit on a CU); each walks its tiles with a grid stride.
     const int threads = 1 << (a.L - K);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
-        per_cu <= 0) {
-        (void)hipGetLastError();
-        per_cu = 1;
-    }
+    int per_cu = 1;
+    hipError_t e = resident_per_cu(kern, c64, threads, lds, &per_cu);
+    if (e != hipSuccess) return e;
     const uint64_t want = uint64_t(cu_count()) * uint64_t(per_cu);
     const unsigned grid = unsigned(a.ntiles < want ? a.ntiles : want);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);

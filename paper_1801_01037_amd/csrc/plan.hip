@@ -22,6 +22,7 @@
 //     Storage of the State Vector): a pass writes its tile back with the
 //     qubits the next gates need in the index bits every tile must hold.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1126,55 +1127,109 @@ static sv_status stage_upload(sv_state s, size_t bytes, const std::function<void
     return SV_OK;
 }
 
-static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
-                           std::string *err)
+// A gate list planned into tile passes, with the layout of what the passes
+// read from device memory: groups | ops | diagonal tables | phase table.
+struct TileRun {
+    TileGeom geo;
+    Flat f;
+    size_t off_ops = 0, off_dtab = 0, off_tab = 0, total = 0;
+};
+
+static sv_status tile_plan(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
+                           TileRun *r, std::string *err)
 {
-    const TileGeom geo = geometry(s->n, s->dt);
+    r->geo = geometry(s->n, s->dt);
     std::vector<Item> items;
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
     bool ok = true;
-    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok, relabel);
+    const std::vector<PPass> passes = plan_passes(s->n, r->geo, items, &ok, relabel);
     if (!ok) {
         *err = "planner could not place every gate with this tile geometry";
         return SV_EUNSUPPORTED;
     }
-    Flat f = flatten(s->n, geo, passes);
-    if (!f.ok) {
+    r->f = flatten(s->n, r->geo, passes);
+    if (!r->f.ok) {
         *err = "planner left a diagonal pair term outside the tile";
         return SV_EUNSUPPORTED;
     }
-
     const bool c64 = s->dt == SV_C64;
     const size_t tab_bytes = 512 * (c64 ? sizeof(float2) : sizeof(double2));
-    const size_t off_groups = 0;
-    const size_t off_ops = align_up(off_groups + f.groups.size() * sizeof(TileGroup), 256);
-    const size_t off_dtab = align_up(off_ops + f.ops.size() * sizeof(TileOp), 256);
-    const size_t off_tab = align_up(off_dtab + f.dtab.size() * sizeof(uint64_t), 256);
-    const size_t total = off_tab + tab_bytes;
+    r->off_ops = align_up(r->f.groups.size() * sizeof(TileGroup), 256);
+    r->off_dtab = align_up(r->off_ops + r->f.ops.size() * sizeof(TileOp), 256);
+    r->off_tab = align_up(r->off_dtab + r->f.dtab.size() * sizeof(uint64_t), 256);
+    r->total = r->off_tab + tab_bytes;
+    return SV_OK;
+}
+
+static void tile_fill(const TileRun &r, bool c64, char *h)
+{
+    std::memcpy(h, r.f.groups.data(), r.f.groups.size() * sizeof(TileGroup));
+    std::memcpy(h + r.off_ops, r.f.ops.data(), r.f.ops.size() * sizeof(TileOp));
+    std::memcpy(h + r.off_dtab, r.f.dtab.data(), r.f.dtab.size() * sizeof(uint64_t));
+    if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + r.off_tab));
+    else fill_phase_table(reinterpret_cast<double2 *>(h + r.off_tab));
+}
+
+// Pass p's kernel arguments, with its tables at device address d.
+static TileArgs tile_args(const TileRun &r, size_t p, void *psi, char *d)
+{
+    TileArgs a = r.f.args[p];
+    a.psi = psi;
+    a.groups = reinterpret_cast<const TileGroup *>(d);
+    a.ops = reinterpret_cast<const TileOp *>(d + r.off_ops);
+    a.dtab = reinterpret_cast<const uint64_t *>(d + r.off_dtab);
+    a.phase_tab = d + r.off_tab;
+    return a;
+}
+
+static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
+                           std::string *err)
+{
+    TileRun r;
+    if (sv_status st = tile_plan(s, gates, n_gates, relabel, &r, err)) return st;
+    const bool c64 = s->dt == SV_C64;
     char *d = nullptr;
-    sv_status st = stage_upload(s, total, [&](char *h) {
-        std::memcpy(h + off_groups, f.groups.data(), f.groups.size() * sizeof(TileGroup));
-        std::memcpy(h + off_ops, f.ops.data(), f.ops.size() * sizeof(TileOp));
-        std::memcpy(h + off_dtab, f.dtab.data(), f.dtab.size() * sizeof(uint64_t));
-        if (c64) fill_phase_table(reinterpret_cast<float2 *>(h + off_tab));
-        else fill_phase_table(reinterpret_cast<double2 *>(h + off_tab));
-    }, &d, err);
+    sv_status st = stage_upload(s, r.total, [&](char *h) { tile_fill(r, c64, h); }, &d, err);
     if (st != SV_OK) return st;
 
     const double bytes = 2.0 * std::ldexp(1.0, s->n) * elem_bytes(s->dt);
-    for (size_t p = 0; p < f.args.size(); ++p) {
-        TileArgs a = f.args[p];
-        a.psi = s->psi;
-        a.groups = reinterpret_cast<const TileGroup *>(d + off_groups);
-        a.ops = reinterpret_cast<const TileOp *>(d + off_ops);
-        a.dtab = reinterpret_cast<const uint64_t *>(d + off_dtab);
-        a.phase_tab = d + off_tab;
+    for (size_t p = 0; p < r.f.args.size(); ++p) {
+        const TileArgs a = tile_args(r, p, s->psi, d);
         const int tok = prof_begin(s);
-        hipError_t e = launch_tile(a, geo.K, c64, s->stream);
-        prof_end(s, tok, KC_TILE, bytes, f.flops[p]);
+        hipError_t e = launch_tile(a, r.geo.K, c64, s->stream);
+        prof_end(s, tok, KC_TILE, bytes, r.f.flops[p]);
         if (e != hipSuccess) { *err = std::string("tile launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
     }
+    return SV_OK;
+}
+
+sv_status tiles_prepare(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel, void **dev,
+                        std::vector<TileArgs> *launches, int *K, std::string *err)
+{
+    TileRun r;
+    if (sv_status st = tile_plan(s, gates, n_gates, relabel, &r, err)) return st;
+    std::vector<char> h(r.total);
+    tile_fill(r, s->dt == SV_C64, h.data());
+    *dev = nullptr;
+    hipError_t e = hipMalloc(dev, r.total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *dev = nullptr;
+        *err = "device allocation of the tile plan failed";
+        return SV_ENOMEM;
+    }
+    e = hipMemcpy(*dev, h.data(), r.total, hipMemcpyHostToDevice);   // synchronous, once
+    if (e != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        *err = hipGetErrorString(e);
+        return SV_EDEVICE;
+    }
+    launches->clear();
+    for (size_t p = 0; p < r.f.args.size(); ++p)
+        launches->push_back(tile_args(r, p, s->psi, static_cast<char *>(*dev)));
+    *K = r.geo.K;
     return SV_OK;
 }
 
@@ -1204,6 +1259,46 @@ static sv_status run_dense(sv_state s, const sv_gate *gates, size_t n_gates, std
         hipError_t e = launch_dense5(a, c64, s->stream);
         prof_end(s, tok, KC_DENSE, 2.0 * N * elem_bytes(s->dt), 256.0 * N);
         if (e != hipSuccess) { *err = std::string("dense launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
+    }
+    return SV_OK;
+}
+
+sv_status dense_prepare(sv_state s, const sv_gate *gates, size_t n_gates, void **dev,
+                        std::vector<DenseArgs> *launches, std::string *err)
+{
+    const std::vector<DBlock> blocks = plan_dense(s->n, gates, n_gates);
+    const bool c64 = s->dt == SV_C64;
+    const size_t mat_bytes = 64 * 64 * (c64 ? sizeof(float) : sizeof(double));
+    std::vector<char> h(std::max<size_t>(blocks.size(), 1) * mat_bytes);
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        if (c64) block_matrix(blocks[b], gates, reinterpret_cast<float *>(h.data() + b * mat_bytes));
+        else block_matrix(blocks[b], gates, reinterpret_cast<double *>(h.data() + b * mat_bytes));
+    }
+    *dev = nullptr;
+    hipError_t e = hipMalloc(dev, h.size());
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *dev = nullptr;
+        *err = "device allocation of the dense blocks failed";
+        return SV_ENOMEM;
+    }
+    e = hipMemcpy(*dev, h.data(), h.size(), hipMemcpyHostToDevice);   // synchronous, once
+    if (e != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        *err = hipGetErrorString(e);
+        return SV_EDEVICE;
+    }
+    const uint64_t all = (uint64_t(1) << s->n) - 1;
+    launches->clear();
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        DenseArgs a{};
+        a.psi = s->psi;
+        a.mat = static_cast<char *>(*dev) + b * mat_bytes;
+        a.bmask = blocks[b].qmask;
+        a.omask = all & ~blocks[b].qmask;
+        a.ncols = uint64_t(1) << (s->n - 5);
+        launches->push_back(a);
     }
     return SV_OK;
 }
@@ -1295,10 +1390,6 @@ sv_status apply_unitary(sv_state s, const int32_t *q, int k, const double *u, st
 sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags,
                    std::string *err)
 {
-    if (flags & SV_GRAPH) {
-        *err = "SV_GRAPH applies to sv_batch_run only";
-        return SV_EUNSUPPORTED;
-    }
     // Dense blocks need at least 16 columns of 32 amplitudes (n >= 9); smaller
     // registers are fused into tiles instead.
     if ((flags & SV_FUSE_DENSE) && s->n >= 9) return run_dense(s, gates, n_gates, err);
@@ -1389,6 +1480,9 @@ int wall_clock_khz()
 }  // namespace svk
 
 struct sv_plan_s {
+    // Distinct for every plan the process creates (never reused, unlike the
+    // address of a destroyed plan): what a batch's captured graph is keyed on.
+    uint64_t serial = 0;
     sv_state st = nullptr;
     int n = 0;
     sv_dtype dt = SV_C128;
@@ -1449,7 +1543,8 @@ sv_status berr(sv_status st, const std::string &m) { return svk::set_error(st, m
 
 namespace svk {
 
-sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out, std::string *err)
+sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan *out, std::string *err,
+                      bool relabel)
 {
     if (s->n < 4) {
         *err = "planned circuits need at least 4 qubits";
@@ -1460,7 +1555,7 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
     bool ok = true;
-    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok, true);
+    const std::vector<PPass> passes = plan_passes(s->n, geo, items, &ok, relabel);
     if (!ok) {
         *err = "planner could not place every gate with this tile geometry";
         return SV_EUNSUPPORTED;
@@ -1482,8 +1577,10 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
     std::memcpy(h.data() + off_dtab, f.dtab.data(), f.dtab.size() * sizeof(uint64_t));
     if (c64) fill_phase_table(reinterpret_cast<float2 *>(h.data() + off_tab));
     else fill_phase_table(reinterpret_cast<double2 *>(h.data() + off_tab));
+    static std::atomic<uint64_t> next_serial{1};
     sv_plan p = new (std::nothrow) sv_plan_s;
     if (!p) { *err = "host allocation failed"; return SV_ENOMEM; }
+    p->serial = next_serial.fetch_add(1);
     hipError_t e = hipMalloc(&p->dev, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1895,7 +1992,7 @@ sv_status sv_batch_run(sv_batch b, const sv_plan *plans, const int32_t *first_pa
             return berr(SV_EINVAL, "pass range outside a plan");
         for (size_t j = 0; j < i; ++j)
             if (plans[j]->st == p->st) return berr(SV_EINVAL, "two plans of one state in a batch");
-        key.push_back(reinterpret_cast<uintptr_t>(p));
+        key.push_back(uintptr_t(p->serial));
         key.push_back(uintptr_t(first[i]));
         key.push_back(uintptr_t(cnt[i]));
     }

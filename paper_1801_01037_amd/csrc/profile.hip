@@ -12,7 +12,7 @@ const char *class_name(int cls)
 {
     static const char *names[KC_COUNT] = {"init", "pair", "pair_ctrl", "swap", "diag",
                                           "tile", "dense", "norm", "probs", "batch",
-                                          "sample"};
+                                          "sample", "graph"};
     return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "?";
 }
 

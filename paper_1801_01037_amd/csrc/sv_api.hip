@@ -184,6 +184,8 @@ sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
 
 namespace svk {
 
+sv_status queue_gate(sv_state s, const sv_gate &g) { return ::queue_gate(s, g); }
+
 sv_status set_error(sv_status st, const std::string &msg)
 {
     g_err = msg;
@@ -270,6 +272,7 @@ sv_status sv_destroy(sv_state s)
     if (!s) return SV_OK;
     DeviceScope ds(s->device);
     hipError_t e = hipStreamSynchronize(s->stream);
+    svk::circuit_graph_release(s);
     svk::plan_release(s);
     svk::prof_release(s);
     if (s->scratch) (void)hipFree(s->scratch);
@@ -403,7 +406,13 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(s, gates[i], i)) return st;
     DeviceScope ds(s->device);
-    if (flags & (SV_FUSE | SV_FUSE_DENSE | SV_GRAPH)) {
+    if (flags & SV_GRAPH) {
+        std::string err;
+        sv_status st = svk::circuit_graph_run(s, gates, n_gates, flags, &err);
+        if (st != SV_OK) return fail(st, "%s", err.c_str());
+        return SV_OK;
+    }
+    if (flags & (SV_FUSE | SV_FUSE_DENSE)) {
         // Gates with several controls run as their own launches between the
         // planned segments of the other gates (list order is kept).
         size_t i = 0;

@@ -116,7 +116,7 @@ bool is_phase_diag(const double m[8]);    // diag(1, e^{i phi}) with |e^{i phi}|
 // Kernel classes reported by sv_profile_read, in this order.
 enum KernelClass {
     KC_INIT = 0, KC_PAIR, KC_PAIR_CTRL, KC_SWAP, KC_DIAG, KC_TILE, KC_DENSE, KC_NORM,
-    KC_PROBS, KC_BATCH, KC_SAMPLE, KC_COUNT
+    KC_PROBS, KC_BATCH, KC_SAMPLE, KC_GRAPH, KC_COUNT
 };
 const char *class_name(int cls);
 
@@ -172,6 +172,7 @@ struct sv_state_s {
     uint64_t sample_cap = 0;          // its size in doubles
     svk::Profiler prof;
     void *plan = nullptr;             // planner buffers (plan.hip)
+    void *graph = nullptr;            // captured circuit graph (graph.hip)
 };
 
 namespace svk {

@@ -152,6 +152,41 @@ def test_run_plan_matches_fused_run():
     assert np.array_equal(got, _run_alone(n, dtype, g))
 
 
+def test_graph_recaptured_after_a_plan_is_replaced():
+    """A captured batch graph belongs to the plans it was captured for: after a
+    plan is destroyed and another one made (often at the same host address),
+    the next SV_GRAPH run captures again and runs the new plan's passes."""
+    dtype = sv.SV_C64
+    specs = _specs(4, 77, 12, 14, 4, 10)
+    states = [sv.sv_create(n, dtype) for n, _, _ in specs]
+    first = [qc.layer_circuit(n, d, s) for n, d, s in specs]
+    second = [qc.layer_circuit(n, d + 3, s + 1) for n, d, s in specs]
+    b = sv.sv_batch_create(dtype)
+    plans = []
+    try:
+        plans = [sv.sv_plan_create(h, g) for h, g in zip(states, first)]
+        sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)
+        outs1 = [sv.sv_copy_out(h) for h in states]
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        plans = []
+        for h in states:
+            sv.sv_reset(h, 0)
+            sv.sv_synchronize(h)
+        plans = [sv.sv_plan_create(h, g) for h, g in zip(states, second)]
+        sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)
+        outs2 = [sv.sv_copy_out(h) for h in states]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    for (n, _, _), g1, g2, o1, o2 in zip(specs, first, second, outs1, outs2):
+        assert np.array_equal(o1, _run_alone(n, dtype, g1))
+        assert np.array_equal(o2, _run_alone(n, dtype, g2))
+
+
 def test_batch_rejects_bad_requests():
     h1 = sv.sv_create(10, sv.SV_C64)
     h2 = sv.sv_create(10, sv.SV_C128)

@@ -102,7 +102,7 @@ def test_no_relabel_rejected_without_fuse():
             sv.sv_run_circuit(h, qc.layer_circuit(6, 2, 1), sv.SV_NO_RELABEL)
         assert e.value.status == sv.SV_EINVAL
         with pytest.raises(sv.SVError) as e:
-            sv.sv_run_circuit(h, qc.layer_circuit(6, 2, 1), sv.SV_GRAPH)
-        assert e.value.status == sv.SV_EUNSUPPORTED
+            sv.sv_run_circuit(h, qc.layer_circuit(6, 2, 1), sv.SV_GRAPH | sv.SV_NO_RELABEL)
+        assert e.value.status == sv.SV_EINVAL
     finally:
         sv.sv_destroy(h)
