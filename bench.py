@@ -6,8 +6,12 @@ One step runs the whole hot path once over the 30-qubit workload:
   reset to |0...0>, 20 random layers (600 Haar SU(2) + 290 CNOT),
   the FP64 norm, and the probabilities of the first 2^20 amplitudes.
 The state lives in HBM the whole time (complex128: 16 GiB; complex64: 8 GiB).
+Circuits run with SV_FUSE | SV_JIT: tile passes, each compiled for its own
+program (compiled during the warm-up steps and kept; passes with diagonal ops
+use the generic tile kernel), planned on the host inside every timed step.
 `value` is gates per second over the timed steps in complex128 (the paper's
-precision); the complex64 run of the same steps is reported beside it.
+precision); the complex64 run of the same steps is reported beside it, and the
+complex128 steps with the generic tile kernel alone in `generic_kernel_c128`.
 Beside the steps (untimed for `value`): a Haar 2x2 gate alone on six targets
 (per-gate passes against the HBM peak), a batch of 512 circuits (p50/p99
 latency), serving samples at the offered rates of --serving-rates, and the
@@ -48,10 +52,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--qubits", type=int, default=WORKLOAD_N)
-    ap.add_argument("--mode", choices=["fused", "pergate", "dense", "sweep", "xl", "cpu_sweep",
-                                       "graph"],
+    ap.add_argument("--mode", choices=["fused", "fused-generic", "pergate", "dense", "sweep", "xl",
+                                       "cpu_sweep", "graph"],
                     default="fused",
-                    help="fused: SV_FUSE tile passes; pergate: one launch per gate; "
+                    help="fused: SV_FUSE | SV_JIT tile passes (each pass compiled for its own "
+                         "program; passes with diagonal ops keep the generic kernel); "
+                         "fused-generic: SV_FUSE with the generic tile kernel only; "
+                         "pergate: one launch per gate; "
                          "dense: SV_FUSE_DENSE 5-qubit blocks on the matrix cores; "
                          "sweep: per-gate timings on every qubit at 30 qubits; "
                          "xl: the 33-qubit complex128 / 34-qubit complex64 depth-10 circuit; "
@@ -62,6 +69,8 @@ def parse():
                     help="CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-generic", action="store_true",
+                    help="skip the c128 steps with the generic tile kernel (mode fused)")
     ap.add_argument("--no-errors", action="store_true",
                     help="skip the error statement (complex64 against complex128 and the oracle)")
     ap.add_argument("--no-batched", action="store_true")
@@ -211,9 +220,11 @@ def precision_errors(sv, torch, n, flags):
     return out
 
 
-KERNEL_SOURCE = {"tile": "kernels_tile.hip", "pair": "kernels_gate.hip",
-                 "pair_ctrl": "kernels_gate.hip", "swap": "kernels_gate.hip",
-                 "diag": "kernels_gate.hip", "dense": "kernels_dense.hip"}
+# The sources of each kernel class (a change in any invalidates its counters).
+KERNEL_SOURCE = {"tile": ("kernels_tile.hip", "tile_dev.h", "jit.hip"),
+                 "pair": ("kernels_gate.hip",), "pair_ctrl": ("kernels_gate.hip",),
+                 "swap": ("kernels_gate.hip",), "diag": ("kernels_gate.hip",),
+                 "dense": ("kernels_dense.hip",)}
 
 
 def measured_traffic(cls, dtype_tag):
@@ -222,11 +233,14 @@ def measured_traffic(cls, dtype_tag):
     the kernel source changed since the counters were taken."""
     import glob
     import hashlib
-    src = KERNEL_SOURCE.get(cls)
-    if src is None:
+    srcs = KERNEL_SOURCE.get(cls)
+    if srcs is None:
         return None
-    with open(os.path.join(ROOT, "paper_1801_01037_amd", "csrc", src), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in srcs:
+        with open(os.path.join(ROOT, "paper_1801_01037_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()[:16]
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))):
         with open(path) as f:
             for ln in f:
@@ -711,11 +725,19 @@ def main():
                           "config": {"workload": workload, "mode": args.mode},
                           args.mode: extra}))
         return
-    flags = {"fused": sv.SV_FUSE, "pergate": 0, "dense": sv.SV_FUSE_DENSE}[args.mode]
+    flags = {"fused": sv.SV_FUSE | sv.SV_JIT, "fused-generic": sv.SV_FUSE, "pergate": 0,
+             "dense": sv.SV_FUSE_DENSE}[args.mode]
     n = args.qubits
     log(f"[bench] c128 n={n} mode={args.mode} steps={args.steps} warmup={args.warmup}")
     r128 = run_dtype(sv, torch, sv.SV_C128, n, args.steps, args.warmup, flags)
     log(f"[bench] c128 {r128['gates_per_s']:.1f} gates/s, {r128['ms_per_step']:.1f} ms/step")
+    generic = None
+    if args.mode == "fused" and not args.no_generic:
+        # the same steps with the generic tile kernel (no pass compiled)
+        rg = run_dtype(sv, torch, sv.SV_C128, n, args.steps, args.warmup, sv.SV_FUSE)
+        generic = {"value": round(rg["gates_per_s"], 3), "ms_per_step": round(rg["ms_per_step"], 3),
+                   "roofline": roofline(rg, "c128")}
+        log(f"[bench] c128 generic kernel {rg['gates_per_s']:.1f} gates/s")
     out_c64 = None
     if not args.no_c64:
         r64 = run_dtype(sv, torch, sv.SV_C64, n, args.steps, args.warmup, flags)
@@ -729,7 +751,7 @@ def main():
             log("[bench] error statement: complex64 against complex128 and the oracle")
             out_c64["errors"] = precision_errors(sv, torch, n, flags)
     pergate = None
-    if not args.no_pergate and args.mode == "fused":
+    if not args.no_pergate and args.mode in ("fused", "fused-generic"):
         log("[bench] per-gate 1q passes")
         pergate = run_pergate_1q(sv, torch, n)
     batched = None
@@ -773,6 +795,7 @@ def main():
         "roofline": roofline(r128, "c128"),
         "cpu_baseline": cpu,
         "c64": out_c64,
+        "generic_kernel_c128": generic,
         "pergate_1q": pergate,
         "batched": batched,
         "serving": serving_stats,

@@ -62,13 +62,18 @@ enum {
     SV_G_CPHASE = 2,  /* diag(1, e^{i theta}) on `target` where bit `control` is 1; */
                       /* theta = m[0] in radians (controlled-phase R_k has         */
                       /* theta = 2 pi / 2^k)                                       */
-    SV_G_MCU = 3      /* 2x2 matrix m on `target` where every bit of a control     */
+    SV_G_MCU = 3,     /* 2x2 matrix m on `target` where every bit of a control     */
                       /* mask is 1 (Toffoli: two controls, m = X); the mask's low  */
                       /* 32 bits are in `control`, its high 32 bits in `flags`    */
+    SV_G_UNITARY = 4  /* a general gate on k = `control` qubits (1 <= k <= 5), as  */
+                      /* sv_apply_unitary applies it: qubit j of its list in bits  */
+                      /* 6j..6j+5 of `flags` (j = 0 is the least significant bit  */
+                      /* of the local index); `target` = index of its matrix in    */
+                      /* the table given to sv_run_circuit_ex; m unused           */
 };
 
 /* One gate of a circuit: 80 bytes, the same record the seeded generators
- * write. `flags` must be 0 except for SV_G_MCU. */
+ * write. `flags` must be 0 except for SV_G_MCU and SV_G_UNITARY. */
 typedef struct {
     int32_t kind;
     int32_t control;    /* -1 when the gate has no control */
@@ -97,6 +102,13 @@ typedef struct {
 #define SV_NO_RELABEL  8u  /* with SV_FUSE: keep the standard storage order between */
                            /* passes (qubits 0..2, or 0..3 for complex64, in every  */
                            /* tile)                                                  */
+#define SV_JIT        16u  /* with SV_FUSE: run each pass with a kernel compiled at */
+                           /* run time (hipRTC) for that pass's program: its ops'   */
+                           /* kinds and register positions fixed in the code, the   */
+                           /* numbers still read from the plan. The first call of a */
+                           /* program shape compiles it (about a second; passes in  */
+                           /* parallel); kernels are kept for the process. Same     */
+                           /* arithmetic as the generic pass kernel                  */
 
 /* ABI version; bumped when a signature or struct changes. */
 int sv_version(void);
@@ -177,7 +189,10 @@ sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
  * | SV_NO_RELABEL) or SV_FUSE_DENSE, each optionally | SV_GRAPH. Fusion
  * reorders only gates that act on disjoint qubits, so the result equals the
  * in-order product up to rounding. All gates are validated before any work is
- * queued.
+ * queued. Gates with several controls (SV_G_MCU) join tile passes like any
+ * other 2x2 (controls in the tile are tested per amplitude, controls outside
+ * it per tile); with SV_FUSE_DENSE, one of at most five qubits joins a dense
+ * block and a wider one runs as its own launch.
  * SV_GRAPH: the first call plans the list, uploads what its kernels read into
  * buffers of its own and captures the launches (no copies, no memsets) in a
  * HIP graph held by the handle; a later call with the same gate list (compared
@@ -188,12 +203,24 @@ sv_status sv_apply_cphase(sv_state s, int control, int target, double theta);
  * graph and capture anew. sv_destroy frees it. */
 sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags);
 
+/* sv_run_circuit for gate lists that also hold general k-qubit gates
+ * (SV_G_UNITARY records): mats is a table of n_mats matrices, entry j at
+ * mats + 2048 j (2 * 32 * 32 doubles; a k-qubit gate uses the first 2 * 4^k,
+ * its 2^k x 2^k complex matrix row major, (re, im) interleaved), read during
+ * the call only. Each such gate runs as sv_apply_unitary would, between the
+ * planned segments of the other gates (list order is kept). SV_GRAPH does not
+ * take such records (SV_EUNSUPPORTED). With mats = NULL and n_mats = 0 this is
+ * sv_run_circuit. SV_EINVAL for a record with a bad qubit list or a matrix
+ * index at or above n_mats. */
+sv_status sv_run_circuit_ex(sv_state s, const sv_gate *gates, size_t n_gates, const double *mats,
+                            size_t n_mats, uint32_t flags);
+
 /* Runs count independent circuits, circuits[c] (lens[c] gates) on states[c],
  * with their work overlapping on the device: the circuit of section Quantum
  * Circuits applied to many registers at once. Each result equals
  * sv_run_circuit(states[c], circuits[c], lens[c], SV_FUSE) bit for bit.
  * States must be distinct and may mix dtypes, sizes and streams. Circuits on
- * n >= 4 qubits without several-control gates go into one batch per dtype
+ * n >= 4 qubits go into one batch per dtype
  * (see sv_batch_run: default launch configuration, circuits of 4096 tiles per
  * pass and more, n >= 24, pass by pass as sv_batch_solo), queued on the stream of
  * that dtype's first such state after the earlier work of every member's
@@ -351,6 +378,14 @@ sv_status sv_batch_times(sv_batch b, double *start_ms, double *end_ms, size_t co
 sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
                           uint32_t flags, int32_t *gate_op, int32_t *n_passes, int32_t *n_groups,
                           int32_t *n_ops);
+
+/* Plans a gate list for SV_FUSE | SV_JIT on the host only and compiles the
+ * kernels of its distinct pass programs with hipRTC, without touching a device
+ * and without keeping them: *n_programs (may be NULL) receives how many there
+ * are. flags: SV_FUSE | SV_JIT, optionally | SV_NO_RELABEL. SV_EDEVICE with the
+ * compiler's log if a program does not compile. */
+sv_status sv_plan_jit_check(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
+                            uint32_t flags, int32_t *n_programs);
 
 /* Plans a gate list for SV_FUSE_DENSE on the host only: *n_blocks blocks of
  * five qubits each. For the first `cap` blocks, block_masks[b] (may be NULL)

@@ -153,19 +153,35 @@ def apply_cphase(psi: np.ndarray, c: int, t: int, theta: float) -> None:
     lib().orc_apply_cphase(_dp(psi.view(np.float64)), n, c, t, float(theta))
 
 
-def run_circuit(psi: np.ndarray, gates: np.ndarray) -> None:
-    """Applies a gate list (qcircuits.GATE_DTYPE records) in place."""
+def run_circuit(psi: np.ndarray, gates: np.ndarray, mats=None) -> None:
+    """Applies a gate list (qcircuits.GATE_DTYPE records) in place, in order.
+    General-gate records (kind 4) take their matrix from the side table
+    `mats` (one row of 2048 doubles per matrix) and are applied by
+    apply_unitary; runs of the other records by the C loop."""
     n = _check_state(psi)
     gates = np.ascontiguousarray(gates)
-    rc = lib().orc_run_circuit(_dp(psi.view(np.float64)), n,
-                               gates.ctypes.data, len(gates))
-    if rc != 0:
-        raise ValueError("malformed gate record")
+    general = np.flatnonzero(gates["kind"] == 4) if len(gates) else np.zeros(0, int)
+    start = 0
+    for i in list(general) + [len(gates)]:
+        if i > start:
+            part = np.ascontiguousarray(gates[start:i])
+            rc = lib().orc_run_circuit(_dp(psi.view(np.float64)), n, part.ctypes.data, len(part))
+            if rc != 0:
+                raise ValueError("malformed gate record")
+        if i < len(gates):
+            g = gates[i]
+            k = int(g["control"])
+            packed = int(np.array(g["flags"], dtype=np.int32).view(np.uint32))
+            qubits = [(packed >> (6 * j)) & 63 for j in range(k)]
+            d = 1 << k
+            row = np.asarray(mats[int(g["target"])], dtype=np.float64)[:2 * d * d]
+            apply_unitary(psi, qubits, row.view(np.complex128).reshape(d, d))
+        start = i + 1
 
 
-def simulate(n: int, gates: np.ndarray, x: int = 0) -> np.ndarray:
+def simulate(n: int, gates: np.ndarray, x: int = 0, mats=None) -> np.ndarray:
     psi = basis_state(n, x)
-    run_circuit(psi, gates)
+    run_circuit(psi, gates, mats)
     return psi
 
 

@@ -77,8 +77,23 @@ def operator_cphase(n: int, c: int, t: int, theta: float) -> np.ndarray:
     return operator_ctrl(n, c, t, np.diag([1.0, np.exp(1j * theta)]))
 
 
-def gate_operator(n: int, g) -> np.ndarray:
+def _table_matrix(g, mats) -> np.ndarray:
+    """A general gate's 2^k x 2^k matrix from its side-table row."""
+    k = int(g["control"])
+    d = 1 << k
+    row = np.asarray(mats[int(g["target"])], dtype=np.float64)[:2 * d * d]
+    return row.view(np.complex128).reshape(d, d)
+
+
+def _record_qubits(g) -> list:
+    packed = int(np.array(g["flags"], dtype=np.int32).view(np.uint32))
+    return [(packed >> (6 * j)) & 63 for j in range(int(g["control"]))]
+
+
+def gate_operator(n: int, g, mats=None) -> np.ndarray:
     kind, c, t = int(g["kind"]), int(g["control"]), int(g["target"])
+    if kind == 4:   # general gate on the listed qubits, matrix from the side table
+        return operator_unitary(n, _record_qubits(g), _table_matrix(g, mats))
     if kind == 0:
         return operator_1q(n, t, matrix_of(g["m"]))
     if kind == 1:
@@ -93,13 +108,14 @@ def gate_operator(n: int, g) -> np.ndarray:
     raise ValueError(f"unknown gate kind {kind}")
 
 
-def run_circuit(n: int, gates, psi0: np.ndarray) -> np.ndarray:
-    """psi = U_G ... U_1 psi0 with every U_g built densely."""
+def run_circuit(n: int, gates, psi0: np.ndarray, mats=None) -> np.ndarray:
+    """psi = U_G ... U_1 psi0 with every U_g built densely (`mats`: the side
+    table of general-gate records)."""
     if n > MAX_QUBITS:
         raise ValueError("the dense tier is for n <= 10")
     psi = np.array(psi0, dtype=np.complex128)
     for g in gates:
-        psi = gate_operator(n, g) @ psi
+        psi = gate_operator(n, g, mats) @ psi
     return psi
 
 

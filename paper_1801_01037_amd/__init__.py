@@ -17,12 +17,12 @@ import os
 import numpy as np
 
 __all__ = [
-    "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SVError", "lib",
+    "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SV_JIT", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
     "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_sample_device_noalloc", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
-    "sv_run_circuit", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device", "sv_compare",
+    "sv_run_circuit", "sv_run_circuit_ex", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device", "sv_compare",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
-    "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_create", "sv_plan_destroy",
+    "sv_plan_inspect", "sv_plan_dense_inspect", "sv_plan_jit_check", "sv_plan_create", "sv_plan_destroy",
     "sv_plan_passes", "sv_run_plan", "sv_batch_create", "sv_batch_destroy", "sv_batch_config",
     "sv_batch_persist", "sv_batch_solo", "sv_batch_run", "sv_batch_times", "StateVector", "LIB_PATH",
 ]
@@ -35,6 +35,7 @@ SV_FUSE = 1
 SV_FUSE_DENSE = 2
 SV_GRAPH = 4
 SV_NO_RELABEL = 8
+SV_JIT = 16
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_EUNSUPPORTED = 0, -1, -2, -3, -4
 _STATUS_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM",
@@ -81,6 +82,7 @@ _SIGNATURES = {
     "sv_sample_device_noalloc": ([_vp, _vp, ctypes.c_uint64, _vp], _int),
     "sv_apply_cphase": ([_vp, _int, _int, ctypes.c_double], _int),
     "sv_run_circuit": ([_vp, _vp, _sz, _u32], _int),
+    "sv_run_circuit_ex": ([_vp, _vp, _sz, _vp, _sz, _u32], _int),
     "sv_run_batch": ([_vp, _vp, _vp, _sz, _u32], _int),
     "sv_probs": ([_vp, _u64, _u64, _dp], _int),
     "sv_probs_device": ([_vp, _u64, _u64, _vp], _int),
@@ -95,6 +97,7 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _int),
     "sv_plan_dense_inspect": ([_int, _vp, _sz, _vp, _vp, ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_int32)], _int),
+    "sv_plan_jit_check": ([_int, _int, _vp, _sz, _u32, ctypes.POINTER(ctypes.c_int32)], _int),
     "sv_plan_create": ([_vp, _vp, _sz, ctypes.POINTER(_vp)], _int),
     "sv_plan_destroy": ([_vp], _int),
     "sv_plan_passes": ([_vp, ctypes.POINTER(ctypes.c_int32)], _int),
@@ -232,11 +235,18 @@ def sv_apply_cphase(h: int, control: int, target: int, theta: float) -> None:
     _check(lib().sv_apply_cphase(h, control, target, float(theta)))
 
 
-def sv_run_circuit(h: int, gates: np.ndarray, flags: int = 0) -> None:
-    g = np.ascontiguousarray(gates)
-    if g.dtype != GATE_DTYPE:
-        g = g.astype(GATE_DTYPE)
-    _check(lib().sv_run_circuit(h, g.ctypes.data if len(g) else None, len(g), flags))
+def sv_run_circuit(h: int, gates: np.ndarray, flags: int = 0, mats=None) -> None:
+    """Runs a gate list; `mats` (qcircuits.unitary_table) is the matrix table of
+    its SV_G_UNITARY records, if any (sv_run_circuit_ex)."""
+    g = _gates(gates)
+    ptr = g.ctypes.data if len(g) else None
+    if mats is None:
+        _check(lib().sv_run_circuit(h, ptr, len(g), flags))
+        return
+    t = np.ascontiguousarray(mats, dtype=np.float64)
+    if t.ndim != 2 or t.shape[1] != 2048:
+        raise ValueError("mats: one row of 2048 doubles per matrix")
+    _check(lib().sv_run_circuit_ex(h, ptr, len(g), t.ctypes.data if len(t) else None, len(t), flags))
 
 
 def sv_run_batch(handles, circuits, flags: int = 0) -> None:
@@ -349,6 +359,17 @@ def sv_plan_dense_inspect(n_qubits: int, gates: np.ndarray, cap: int | None = No
     return masks, mats
 
 
+def sv_plan_jit_check(n_qubits: int, dtype: int, gates: np.ndarray,
+                      flags: int = SV_FUSE | SV_JIT) -> int:
+    """Host only: compiles the pass programs SV_FUSE | SV_JIT would run for
+    this gate list; returns their number (see include/sv.h)."""
+    g = _gates(gates)
+    nprog = ctypes.c_int32()
+    _check(lib().sv_plan_jit_check(n_qubits, dtype, g.ctypes.data if len(g) else None, len(g),
+                                   flags, ctypes.byref(nprog)))
+    return nprog.value
+
+
 def _gates(gates):
     g = np.ascontiguousarray(gates)
     if g.dtype != GATE_DTYPE:
@@ -452,8 +473,8 @@ class StateVector:
     def apply_cphase(self, control, target, theta):
         sv_apply_cphase(self.handle, control, target, theta)
 
-    def run(self, gates, flags: int = 0):
-        sv_run_circuit(self.handle, gates, flags)
+    def run(self, gates, flags: int = 0, mats=None):
+        sv_run_circuit(self.handle, gates, flags, mats)
 
     def probs(self, first: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:

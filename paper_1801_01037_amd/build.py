@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsv.so")
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 ARCH = "gfx950"
 
 # -simplifycfg-sink-common=false: sinking the common code of switch arms into
@@ -24,7 +25,24 @@ ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-simplifycfg-sink-common=false",
-          "-I", os.path.join(os.path.dirname(HERE), "include")]
+          "-I", os.path.join(os.path.dirname(HERE), "include"), "-I", BUILD]
+
+
+def _write_jit_sources() -> None:
+    """The text of the headers a pass compiled at run time includes, as C
+    string constants (jit_src.inc, included by jit.hip)."""
+    out = []
+    for var, name in (("kTileHSrc", "tile.h"), ("kTileDevHSrc", "tile_dev.h")):
+        with open(os.path.join(CSRC, name)) as f:
+            text = f.read()
+        if ")SVJIT\"" in text:
+            raise RuntimeError(f"{name} contains the raw-string delimiter")
+        out.append(f'static const char {var}[] = R"SVJIT({text})SVJIT";\n')
+    path = os.path.join(BUILD, "jit_src.inc")
+    new = "".join(out)
+    if not os.path.exists(path) or open(path).read() != new:
+        with open(path, "w") as f:
+            f.write(new)
 
 
 def _compile(src: str) -> str:
@@ -42,11 +60,13 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    _write_jit_sources()
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L", os.path.join(ROCM, "lib"), "-lhiprtc"]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     os.replace(tmp, LIB)
     if verbose:

@@ -13,8 +13,8 @@
 // The captured launches are the ones the same flags queue without SV_GRAPH:
 // tile passes (relabelled unless SV_NO_RELABEL) for SV_FUSE, dense 5-qubit
 // blocks for SV_FUSE_DENSE (n >= 9; tile passes below), one launch per gate
-// for SV_GRAPH alone, and one launch per gate with several controls between
-// planned segments. Results are bit for bit those of the same flags without
+// for SV_GRAPH alone, and one launch per gate of more than five qubits between
+// dense segments. Results are bit for bit those of the same flags without
 // SV_GRAPH.
 #include <cmath>
 #include <cstring>
@@ -42,6 +42,7 @@ struct CircuitGraph {
     std::vector<Step> steps;
     std::vector<void *> bufs;           // tile tables and block matrices the graph reads
     std::vector<TileArgs> tiles;
+    std::vector<JitKernel> jit;         // SV_JIT: the compiled kernel of each of `tiles`
     std::vector<DenseArgs> dense;
     hipStream_t capture = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -53,6 +54,7 @@ struct CircuitGraph {
         for (void *d : bufs) (void)hipFree(d);
         bufs.clear();
         tiles.clear();
+        jit.clear();
         dense.clear();
         steps.clear();
     }
@@ -70,9 +72,18 @@ sv_status build_steps(sv_state s, CircuitGraph *g, const sv_gate *gates, size_t 
 {
     const double N = std::ldexp(1.0, s->n), sb = elem_bytes(s->dt);
     const bool fuse = flags & (SV_FUSE | SV_FUSE_DENSE);
+    const bool dense = (flags & SV_FUSE_DENSE) && s->n >= 9;
+    // As without SV_GRAPH: dense blocks hold at most five qubits, so a wider
+    // gate with several controls is a launch of its own there.
+    auto alone = [&](const sv_gate &g) {
+        if (!fuse) return true;
+        if (!dense || g.kind != SV_G_MCU) return false;
+        const uint64_t cm = uint64_t(uint32_t(g.control)) | (uint64_t(uint32_t(g.flags)) << 32);
+        return __builtin_popcountll(cm) + 1 > 5;
+    };
     size_t i = 0;
     while (i < n_gates) {
-        if (!fuse || gates[i].kind == SV_G_MCU) {
+        if (alone(gates[i])) {
             Step st;
             st.kind = Step::GATE;
             st.gate = gates[i];
@@ -82,7 +93,7 @@ sv_status build_steps(sv_state s, CircuitGraph *g, const sv_gate *gates, size_t 
             continue;
         }
         size_t j = i;
-        while (j < n_gates && gates[j].kind != SV_G_MCU) ++j;
+        while (j < n_gates && !alone(gates[j])) ++j;
         Step st;
         void *dev = nullptr;
         if ((flags & SV_FUSE_DENSE) && s->n >= 9) {
@@ -95,12 +106,14 @@ sv_status build_steps(sv_state s, CircuitGraph *g, const sv_gate *gates, size_t 
             g->flops += 256.0 * N * double(blocks.size());
         } else {
             std::vector<TileArgs> passes;
+            std::vector<JitKernel> kern;
             if (sv_status r = tiles_prepare(s, gates + i, j - i, !(flags & SV_NO_RELABEL), &dev,
-                                            &passes, &st.K, err))
+                                            &passes, &st.K, (flags & SV_JIT) ? &kern : nullptr, err))
                 return r;
             st.kind = Step::TILES;
             st.first = g->tiles.size();
             g->tiles.insert(g->tiles.end(), passes.begin(), passes.end());
+            if (flags & SV_JIT) g->jit.insert(g->jit.end(), kern.begin(), kern.end());
             st.last = g->tiles.size();
         }
         g->bufs.push_back(dev);
@@ -120,7 +133,8 @@ sv_status queue_steps(sv_state s, const CircuitGraph &g, std::string *err)
         switch (st.kind) {
         case Step::TILES:
             for (size_t p = st.first; p < st.last && e == hipSuccess; ++p)
-                e = launch_tile(g.tiles[p], st.K, c64, s->stream);
+                e = g.jit.empty() ? launch_tile(g.tiles[p], st.K, c64, s->stream)
+                                  : jit_launch(g.jit[p], g.tiles[p], st.K, c64, s->stream);
             break;
         case Step::DENSE:
             for (size_t b = st.first; b < st.last && e == hipSuccess; ++b)
@@ -201,7 +215,7 @@ sv_status circuit_graph_run(sv_state s, const sv_gate *gates, size_t n_gates, ui
 {
     if (!s->graph) s->graph = new CircuitGraph();
     CircuitGraph *g = static_cast<CircuitGraph *>(s->graph);
-    const uint32_t key = flags & (SV_FUSE | SV_FUSE_DENSE | SV_NO_RELABEL);
+    const uint32_t key = flags & (SV_FUSE | SV_FUSE_DENSE | SV_NO_RELABEL | SV_JIT);
     if (!g->exec || g->flags != key || g->psi != s->psi || !same_gates(g->gates, gates, n_gates)) {
         if (g->exec) {
             // Replays of the old graph may still be queued; they read the

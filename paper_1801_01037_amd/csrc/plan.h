@@ -36,8 +36,11 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
 // uploaded once (synchronously) to a device buffer *dev that the caller frees;
 // *launches receives the arguments of one launch_tile per pass, in order, all
 // with register bits *K.
+struct JitKernel;
+// jit: if not null, also compiles the passes (SV_JIT) into (*jit)[p].
 sv_status tiles_prepare(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel, void **dev,
-                        std::vector<TileArgs> *launches, int *K, std::string *err);
+                        std::vector<TileArgs> *launches, int *K, std::vector<JitKernel> *jit,
+                        std::string *err);
 
 // The dense 5-qubit blocks of a validated gate list (n >= 9), their matrices
 // uploaded once (synchronously) to a device buffer *dev that the caller frees;
@@ -53,6 +56,30 @@ sv_status circuit_graph_run(sv_state s, const sv_gate *gates, size_t n_gates, ui
                             std::string *err);
 // Frees the handle's captured circuit graph and the buffers it reads.
 void circuit_graph_release(sv_state s);
+
+// A tile pass compiled for its own program (jit.hip).
+struct JitKernel {
+    hipFunction_t fn;   // null: the pass runs with the generic tile kernel
+    int per_cu;         // resident work-groups per CU
+};
+// Compiles (or finds in the process's cache) one kernel per pass of a plan;
+// groups and ops are the plan's host records (TileArgs.group0 and the groups'
+// op0 index them). On failure returns SV_EDEVICE with the compiler's log.
+sv_status jit_passes(sv_dtype dt, int K, const std::vector<TileArgs> &passes,
+                     const std::vector<TileGroup> &groups, const std::vector<TileOp> &ops,
+                     std::vector<JitKernel> *out, std::string *err);
+// Compiles the distinct programs of a plan's passes on the host only (no
+// device is touched, nothing is cached); *n_programs receives their number.
+bool jit_compile_only(sv_dtype dt, int K, const std::vector<TileArgs> &passes,
+                      const std::vector<TileGroup> &groups, const std::vector<TileOp> &ops,
+                      int32_t *n_programs, std::string *err);
+// Host-only: plans a validated gate list as SV_FUSE does and compiles its pass
+// programs (jit_compile_only). 0 on success, -1 planning failed, -2 compiling.
+int plan_jit_check(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool relabel,
+                   int32_t *n_programs, std::string *err);
+// Launches pass `a` (its device pointers patched) with its compiled kernel,
+// or with the generic one when it has none.
+hipError_t jit_launch(const JitKernel &k, const TileArgs &a, int K, bool c64, hipStream_t st);
 
 // One gate as its own launch (sv_api.hip).
 sv_status queue_gate(sv_state s, const sv_gate &g);

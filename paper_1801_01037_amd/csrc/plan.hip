@@ -42,6 +42,7 @@ struct Item {
     int gate = -1;
     bool diag = false;
     int target = -1, control = -1;   // non-diagonal
+    uint64_t xcm = 0;                // further controls (several-control gates)
     bool swap = false;
     double m[8] = {};
     int pivot = -1, wbit = -1;       // diagonal: pivot bit, weight bit (-1: constant)
@@ -65,6 +66,7 @@ struct PPivot {
 struct POp {
     int kind = TOP_U;
     int target = -1, control = -1;
+    uint64_t xcm = 0;          // TOP_U / TOP_SWAP: controls besides `control`
     double m[8] = {};
     std::vector<PPivot> piv;
     std::vector<int> gates;
@@ -77,7 +79,8 @@ uint64_t op_qmask(const POp &op)
 {
     if (op.kind == TOP_U4) return (uint64_t(1) << op.q0) | (uint64_t(1) << op.q1);
     if (op.kind != TOP_DIAG)
-        return (uint64_t(1) << op.target) | (op.control >= 0 ? uint64_t(1) << op.control : 0);
+        return (uint64_t(1) << op.target) | (op.control >= 0 ? uint64_t(1) << op.control : 0) |
+               op.xcm;
     uint64_t m = 0;
     for (const PPivot &P : op.piv) {
         m |= uint64_t(1) << P.p;
@@ -144,7 +147,7 @@ constexpr double kPassFloor = 415.0;  // a pass's HBM time on the same scale
 std::vector<POp> fuse_group(std::vector<POp> ops, uint64_t regq, bool spread)
 {
     auto absorbable = [&](const POp &op) {
-        if (op.kind != TOP_U && op.kind != TOP_SWAP) return false;
+        if ((op.kind != TOP_U && op.kind != TOP_SWAP) || op.xcm) return false;
         return op.control < 0 || ((regq >> op.control) & 1);
     };
     std::vector<uint64_t> qmask(ops.size());
@@ -287,7 +290,7 @@ void fold_exit(PGroup &g, const std::vector<int> &T)
     for (int i = int(g.ops.size()) - 1; i >= 0; --i) {
         const POp &op = g.ops[i];
         const uint64_t qm = op_qmask(op);
-        const bool exch = op.kind == TOP_SWAP && ((regq >> op.target) & 1) &&
+        const bool exch = op.kind == TOP_SWAP && !op.xcm && ((regq >> op.target) & 1) &&
                           (op.control < 0 || ((regq >> op.control) & 1));
         if (exch && !(qm & kept)) {
             out[i] = 1;
@@ -346,6 +349,9 @@ void to_storage(POp &op, const std::vector<int> &pos)
 {
     if (op.target >= 0) op.target = pos[op.target];
     if (op.control >= 0) op.control = pos[op.control];
+    uint64_t x = 0;
+    for (uint64_t m = op.xcm; m; m &= m - 1) x |= uint64_t(1) << pos[__builtin_ctzll(m)];
+    op.xcm = x;
     for (PPivot &P : op.piv) {
         P.p = pos[P.p];
         for (DTerm &t : P.terms)
@@ -412,6 +418,18 @@ Item classify(const sv_gate &g, int idx)
     Item it;
     it.gate = idx;
     const uint64_t tb = uint64_t(1) << g.target;
+    if (g.kind == SV_G_MCU) {
+        // Several controls: the lowest is `control`, the others go with it
+        // as a mask; never a diagonal term (those hold at most two qubits).
+        const uint64_t cm = uint64_t(uint32_t(g.control)) | (uint64_t(uint32_t(g.flags)) << 32);
+        it.target = g.target;
+        it.control = __builtin_ctzll(cm);
+        it.xcm = cm & (cm - 1);
+        it.swap = is_pauli_x(g.m);
+        std::memcpy(it.m, g.m, sizeof it.m);
+        it.qmask = tb | cm;
+        return it;
+    }
     if (g.kind == SV_G_CPHASE || (g.kind != SV_G_U && is_phase_diag(g.m)) ||
         (g.kind == SV_G_U && is_phase_diag(g.m))) {
         it.diag = true;
@@ -509,7 +527,7 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
             }
             const uint64_t need = op.kind == TOP_U4 ? qm : uint64_t(1) << op.target;
             uint64_t want = need;
-            if (op.kind != TOP_U4 && op.control >= 0 && ((Pm >> op.control) & 1))
+            if (op.kind != TOP_U4 && op.control >= 0 && !op.xcm && ((Pm >> op.control) & 1))
                 want |= uint64_t(1) << op.control;
             if (__builtin_popcountll(Sq | want) <= geo.K) {
                 Sq |= want;
@@ -629,6 +647,7 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
             op.kind = it.swap ? TOP_SWAP : TOP_U;
             op.target = it.target;
             op.control = it.control;
+            op.xcm = it.xcm;
             std::memcpy(op.m, it.m, sizeof op.m);
             op.gates.push_back(it.gate);
             ops.push_back(std::move(op));
@@ -930,7 +949,14 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                     const int p = local(op.target);
                     to.pj = int(std::find(g.S.begin(), g.S.end(), p) - g.S.begin());
                     to.pk = -1;
-                    if (op.control >= 0) {
+                    if (op.xcm) {
+                        // several controls: masks of the tile-bit and the
+                        // outside controls, tested per amplitude and per tile
+                        const uint64_t cm = op.xcm | (uint64_t(1) << op.control);
+                        for (uint64_t m = cm & Tm; m; m &= m - 1)
+                            to.lcm |= 1u << local(__builtin_ctzll(m));
+                        to.ocm = cm & ~Tm;
+                    } else if (op.control >= 0) {
                         if ((Tm >> op.control) & 1) {
                             to.lctrl = local(op.control);
                             const int pc = int(std::find(g.S.begin(), g.S.end(), to.lctrl) - g.S.begin());
@@ -941,7 +967,8 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
                     }
                     std::memcpy(to.m, op.m, sizeof to.m);
                     for (int k = 0; k < 8; ++k) to.mf[k] = float(op.m[k]);
-                    if (op.kind == TOP_U) flops += (op.control >= 0 ? 7.0 : 14.0) * N;
+                    const int nctrl = (op.control >= 0 ? 1 : 0) + __builtin_popcountll(op.xcm);
+                    if (op.kind == TOP_U) flops += std::ldexp(14.0 * N, -nctrl);
                 }
                 f.ops.push_back(to);
             }
@@ -973,12 +1000,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 
-uint64_t gate_qmask(const sv_gate &g)
+// Control qubits of a validated gate record, as a mask.
+uint64_t gate_cmask(const sv_gate &g)
 {
-    uint64_t m = uint64_t(1) << g.target;
-    if (g.kind != SV_G_U) m |= uint64_t(1) << g.control;
-    return m;
+    if (g.kind == SV_G_MCU) return uint64_t(uint32_t(g.control)) | (uint64_t(uint32_t(g.flags)) << 32);
+    return g.kind == SV_G_U ? 0 : uint64_t(1) << g.control;
 }
+
+uint64_t gate_qmask(const sv_gate &g) { return (uint64_t(1) << g.target) | gate_cmask(g); }
 
 struct DBlock {
     uint64_t qmask = 0;
@@ -1043,11 +1072,12 @@ void block_matrix(const DBlock &b, const sv_gate *g, R *out)
             std::memcpy(m, G.m, sizeof m);
         }
         const int t = pos[G.target];
-        const int c = G.kind == SV_G_U ? -1 : pos[G.control];
+        int cm = 0;   // the controls as local bits: the update runs where all are 1
+        for (uint64_t x = gate_cmask(G); x; x &= x - 1) cm |= 1 << pos[__builtin_ctzll(x)];
         for (int col = 0; col < 32; ++col)
             for (int i0 = 0; i0 < 32; ++i0) {
                 if ((i0 >> t) & 1) continue;
-                if (c >= 0 && !((i0 >> c) & 1)) continue;
+                if ((i0 & cm) != cm) continue;
                 const int i1 = i0 | (1 << t);
                 const double ar = re[i0][col], ai = im[i0][col];
                 const double br = re[i1][col], bi = im[i1][col];
@@ -1184,11 +1214,15 @@ static TileArgs tile_args(const TileRun &r, size_t p, void *psi, char *d)
 }
 
 static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
-                           std::string *err)
+                           bool jit, std::string *err)
 {
     TileRun r;
     if (sv_status st = tile_plan(s, gates, n_gates, relabel, &r, err)) return st;
     const bool c64 = s->dt == SV_C64;
+    std::vector<JitKernel> kern;
+    if (jit)
+        if (sv_status st = jit_passes(s->dt, r.geo.K, r.f.args, r.f.groups, r.f.ops, &kern, err))
+            return st;
     char *d = nullptr;
     sv_status st = stage_upload(s, r.total, [&](char *h) { tile_fill(r, c64, h); }, &d, err);
     if (st != SV_OK) return st;
@@ -1197,7 +1231,8 @@ static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, boo
     for (size_t p = 0; p < r.f.args.size(); ++p) {
         const TileArgs a = tile_args(r, p, s->psi, d);
         const int tok = prof_begin(s);
-        hipError_t e = launch_tile(a, r.geo.K, c64, s->stream);
+        hipError_t e = jit ? jit_launch(kern[p], a, r.geo.K, c64, s->stream)
+                           : launch_tile(a, r.geo.K, c64, s->stream);
         prof_end(s, tok, KC_TILE, bytes, r.f.flops[p]);
         if (e != hipSuccess) { *err = std::string("tile launch: ") + hipGetErrorString(e); return SV_EDEVICE; }
     }
@@ -1205,10 +1240,14 @@ static sv_status run_tiles(sv_state s, const sv_gate *gates, size_t n_gates, boo
 }
 
 sv_status tiles_prepare(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel, void **dev,
-                        std::vector<TileArgs> *launches, int *K, std::string *err)
+                        std::vector<TileArgs> *launches, int *K, std::vector<JitKernel> *jit,
+                        std::string *err)
 {
     TileRun r;
     if (sv_status st = tile_plan(s, gates, n_gates, relabel, &r, err)) return st;
+    if (jit)
+        if (sv_status st = jit_passes(s->dt, r.geo.K, r.f.args, r.f.groups, r.f.ops, jit, err))
+            return st;
     std::vector<char> h(r.total);
     tile_fill(r, s->dt == SV_C64, h.data());
     *dev = nullptr;
@@ -1393,7 +1432,7 @@ sv_status plan_run(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t fl
     // Dense blocks need at least 16 columns of 32 amplitudes (n >= 9); smaller
     // registers are fused into tiles instead.
     if ((flags & SV_FUSE_DENSE) && s->n >= 9) return run_dense(s, gates, n_gates, err);
-    return run_tiles(s, gates, n_gates, !(flags & SV_NO_RELABEL), err);
+    return run_tiles(s, gates, n_gates, !(flags & SV_NO_RELABEL), (flags & SV_JIT) != 0, err);
 }
 
 void plan_release(sv_state s)
@@ -1457,6 +1496,26 @@ int plan_inspect(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool 
     if (n_groups) *n_groups = groups;
     if (n_ops) *n_ops = seq;
     return 0;
+}
+
+int plan_jit_check(int n, sv_dtype dt, const sv_gate *gates, size_t n_gates, bool relabel,
+                   int32_t *n_programs, std::string *err)
+{
+    const TileGeom geo = geometry(n, dt);
+    std::vector<Item> items;
+    for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
+    bool ok = true;
+    const std::vector<PPass> passes = plan_passes(n, geo, items, &ok, relabel);
+    if (!ok) {
+        *err = "planner could not place every gate with this tile geometry";
+        return -1;
+    }
+    const Flat f = flatten(n, geo, passes);
+    if (!f.ok) {
+        *err = "planner left a diagonal pair term outside the tile";
+        return -1;
+    }
+    return jit_compile_only(dt, geo.K, f.args, f.groups, f.ops, n_programs, err) ? 0 : -2;
 }
 
 }  // namespace svk

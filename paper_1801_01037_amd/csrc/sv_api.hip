@@ -83,23 +83,28 @@ sv_status make_handle(void *psi, int n, sv_dtype dt, void *stream, bool owned, s
     return SV_OK;
 }
 
-// Planned circuits (tile and dense plans) hold gates with at most one control.
-sv_status reject_mcu(const sv_gate *gates, size_t n_gates)
-{
-    for (size_t i = 0; i < n_gates; ++i)
-        if (gates[i].kind == SV_G_MCU)
-            return fail(SV_EUNSUPPORTED,
-                        "gate %zu: plans do not hold gates with several controls "
-                        "(sv_run_circuit and sv_apply_mcu apply them)", i);
-    return SV_OK;
-}
-
 // The control qubits of a (validated) gate record as a bit mask.
 uint64_t control_mask(const sv_gate &g)
 {
     if (g.kind == SV_G_MCU)
         return uint64_t(uint32_t(g.control)) | (uint64_t(uint32_t(g.flags)) << 32);
     return g.kind == SV_G_U ? 0 : uint64_t(1) << g.control;
+}
+
+// Dense blocks span at most five qubits: a gate with several controls that
+// touches more runs as its own launch between dense segments.
+bool outside_dense_blocks(const sv_gate &g)
+{
+    return g.kind == SV_G_MCU && __builtin_popcountll(control_mask(g)) + 1 > 5;
+}
+
+// Dense plans (host-only inspection) hold gates of at most five qubits.
+sv_status reject_wide(const sv_gate *gates, size_t n_gates)
+{
+    for (size_t i = 0; i < n_gates; ++i)
+        if (outside_dense_blocks(gates[i]))
+            return fail(SV_EUNSUPPORTED, "gate %zu: more than five qubits do not fit a dense block", i);
+    return SV_OK;
 }
 
 // Queues one gate as its own kernel (one pass over the touched amplitudes).
@@ -146,8 +151,35 @@ sv_status queue_gate(sv_state s, const sv_gate &g)
     return SV_OK;
 }
 
-sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx)
+// The qubits of a SV_G_UNITARY record (q[0] first); returns k, or 0 when the
+// list is malformed for an n-qubit register.
+int unitary_qubits(const sv_gate &g, int n, int32_t q[5])
 {
+    const int k = g.control;
+    if (k < 1 || k > 5 || k > n) return 0;
+    if (k < 5 && (uint32_t(g.flags) >> (6 * k)) != 0) return 0;   // stray bits past the list
+    uint64_t seen = 0;
+    for (int j = 0; j < k; ++j) {
+        q[j] = (uint32_t(g.flags) >> (6 * j)) & 63u;
+        if (q[j] >= n || ((seen >> q[j]) & 1)) return 0;
+        seen |= uint64_t(1) << q[j];
+    }
+    return k;
+}
+
+sv_status validate_gate(const sv_state_s *s, const sv_gate &g, size_t idx, size_t n_mats = 0)
+{
+    if (g.kind == SV_G_UNITARY) {
+        int32_t q[5];
+        if (!n_mats)
+            return fail(SV_EINVAL, "gate %zu: SV_G_UNITARY records need the matrix table of "
+                        "sv_run_circuit_ex", idx);
+        if (!unitary_qubits(g, s->n, q))
+            return fail(SV_EINVAL, "gate %zu: malformed qubit list of a SV_G_UNITARY record", idx);
+        if (g.target < 0 || size_t(g.target) >= n_mats)
+            return fail(SV_EINVAL, "gate %zu: matrix index %d not below %zu", idx, g.target, n_mats);
+        return SV_OK;
+    }
     if (g.flags != 0 && g.kind != SV_G_MCU) return fail(SV_EINVAL, "gate %zu: flags must be 0", idx);
     if (g.target < 0 || g.target >= s->n)
         return fail(SV_EINVAL, "gate %zu: target %d out of range [0, %d)", idx, g.target, s->n);
@@ -394,36 +426,76 @@ sv_status sv_apply_cphase(sv_state s, int control, int target, double theta)
 
 sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint32_t flags)
 {
+    return sv_run_circuit_ex(s, gates, n_gates, nullptr, 0, flags);
+}
+
+sv_status sv_run_circuit_ex(sv_state s, const sv_gate *gates, size_t n_gates, const double *mats,
+                            size_t n_mats, uint32_t flags)
+{
     if (sv_status st = check_handle(s)) return st;
     if (n_gates == 0) return SV_OK;
     if (!gates) return fail(SV_EINVAL, "null gate array");
-    if (flags & ~(SV_FUSE | SV_FUSE_DENSE | SV_GRAPH | SV_NO_RELABEL))
+    if (n_mats && !mats) return fail(SV_EINVAL, "null matrix table");
+    if (flags & ~(SV_FUSE | SV_FUSE_DENSE | SV_GRAPH | SV_NO_RELABEL | SV_JIT))
         return fail(SV_EINVAL, "unknown flags 0x%x", flags);
     if ((flags & SV_NO_RELABEL) && !(flags & SV_FUSE))
         return fail(SV_EINVAL, "SV_NO_RELABEL applies to SV_FUSE only");
+    if ((flags & SV_JIT) && !(flags & SV_FUSE))
+        return fail(SV_EINVAL, "SV_JIT applies to SV_FUSE only");
     if ((flags & SV_FUSE) && (flags & SV_FUSE_DENSE))
         return fail(SV_EINVAL, "SV_FUSE and SV_FUSE_DENSE are exclusive");
-    for (size_t i = 0; i < n_gates; ++i)
-        if (sv_status st = validate_gate(s, gates[i], i)) return st;
+    bool any_unitary = false;
+    for (size_t i = 0; i < n_gates; ++i) {
+        if (sv_status st = validate_gate(s, gates[i], i, n_mats)) return st;
+        any_unitary |= gates[i].kind == SV_G_UNITARY;
+    }
+    if (any_unitary)
+        for (size_t i = 0; i < n_gates; ++i)
+            if (gates[i].kind == SV_G_UNITARY)
+                for (int v = 0; v < 2 * (1 << (2 * gates[i].control)); ++v)
+                    if (!std::isfinite(mats[size_t(gates[i].target) * 2048 + size_t(v)]))
+                        return fail(SV_EINVAL, "gate %zu: non-finite matrix entry", i);
     DeviceScope ds(s->device);
+    // A general gate: one launch, as sv_apply_unitary queues it.
+    auto unitary = [&](const sv_gate &g) -> sv_status {
+        int32_t q[5];
+        const int k = unitary_qubits(g, s->n, q);
+        const double *u = mats + size_t(g.target) * 2048;
+        if (k == 1) {
+            sv_gate one{SV_G_U, -1, q[0], 0, {}};
+            std::memcpy(one.m, u, sizeof one.m);
+            return queue_gate(s, one);
+        }
+        std::string err;
+        sv_status st = svk::apply_unitary(s, q, k, u, &err);
+        return st == SV_OK ? SV_OK : fail(st, "%s", err.c_str());
+    };
     if (flags & SV_GRAPH) {
+        if (any_unitary)
+            return fail(SV_EUNSUPPORTED, "SV_GRAPH takes no SV_G_UNITARY records");
         std::string err;
         sv_status st = svk::circuit_graph_run(s, gates, n_gates, flags, &err);
         if (st != SV_OK) return fail(st, "%s", err.c_str());
         return SV_OK;
     }
     if (flags & (SV_FUSE | SV_FUSE_DENSE)) {
-        // Gates with several controls run as their own launches between the
-        // planned segments of the other gates (list order is kept).
+        // Dense blocks hold at most five qubits: wider gates with several
+        // controls run as their own launches between the planned segments of
+        // the other gates (list order is kept), and so do general gates.
+        const bool dense = (flags & SV_FUSE_DENSE) && s->n >= 9;
+        auto alone = [&](const sv_gate &g) {
+            return g.kind == SV_G_UNITARY || (dense && outside_dense_blocks(g));
+        };
         size_t i = 0;
         while (i < n_gates) {
-            if (gates[i].kind == SV_G_MCU) {
-                if (sv_status st = queue_gate(s, gates[i])) return st;
+            if (alone(gates[i])) {
+                sv_status st = gates[i].kind == SV_G_UNITARY ? unitary(gates[i]) : queue_gate(s, gates[i]);
+                if (st != SV_OK) return st;
                 ++i;
                 continue;
             }
             size_t j = i;
-            while (j < n_gates && gates[j].kind != SV_G_MCU) ++j;
+            while (j < n_gates && !alone(gates[j])) ++j;
             std::string err;
             sv_status st = svk::plan_run(s, gates + i, j - i, flags, &err);
             if (st != SV_OK) return fail(st, "%s", err.c_str());
@@ -431,8 +503,10 @@ sv_status sv_run_circuit(sv_state s, const sv_gate *gates, size_t n_gates, uint3
         }
         return SV_OK;
     }
-    for (size_t i = 0; i < n_gates; ++i)
-        if (sv_status st = queue_gate(s, gates[i])) return st;
+    for (size_t i = 0; i < n_gates; ++i) {
+        sv_status st = gates[i].kind == SV_G_UNITARY ? unitary(gates[i]) : queue_gate(s, gates[i]);
+        if (st != SV_OK) return st;
+    }
     return SV_OK;
 }
 
@@ -454,8 +528,8 @@ sv_status sv_run_batch(sv_state *states, const sv_gate *const *circuits, const s
         for (size_t i = 0; i < lens[c]; ++i)
             if (sv_status st = validate_gate(states[c], circuits[c][i], i)) return st;
     }
-    // Circuits the planner takes (n >= 4, no several-control gates) go into one
-    // batch per dtype; the others run alone, planned, on their own streams.
+    // Circuits the planner takes (n >= 4) go into one batch per dtype; the
+    // others run alone, planned, on their own streams.
     std::vector<sv_plan> plans[2];
     std::vector<sv_state> owners[2];
     std::vector<size_t> alone;
@@ -465,9 +539,8 @@ sv_status sv_run_batch(sv_state *states, const sv_gate *const *circuits, const s
     };
     for (size_t c = 0; c < count; ++c) {
         const sv_gate *g = circuits[c];
-        const bool mcu = std::any_of(g, g + lens[c], [](const sv_gate &x) { return x.kind == SV_G_MCU; });
         if (lens[c] == 0) continue;
-        if (states[c]->n < 4 || mcu) {
+        if (states[c]->n < 4) {
             alone.push_back(c);
             continue;
         }
@@ -664,10 +737,30 @@ sv_status sv_plan_inspect(int n_qubits, sv_dtype dtype, const sv_gate *gates, si
     probe.dt = dtype;
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
-    if (sv_status st = reject_mcu(gates, n_gates)) return st;
     if (svk::plan_inspect(n_qubits, dtype, gates, n_gates, !(flags & SV_NO_RELABEL), gate_op, n_passes,
                           n_groups, n_ops) != 0)
         return fail(SV_EUNSUPPORTED, "planner could not place every gate with this tile geometry");
+    return SV_OK;
+}
+
+sv_status sv_plan_jit_check(int n_qubits, sv_dtype dtype, const sv_gate *gates, size_t n_gates,
+                            uint32_t flags, int32_t *n_programs)
+{
+    if (!valid_dtype(dtype)) return fail(SV_EINVAL, "unknown dtype %d", int(dtype));
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d not in [1, 34]", n_qubits);
+    if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
+    if ((flags & ~SV_NO_RELABEL) != (SV_FUSE | SV_JIT))
+        return fail(SV_EINVAL, "flags must be SV_FUSE | SV_JIT, optionally | SV_NO_RELABEL");
+    sv_state_s probe;
+    probe.n = n_qubits;
+    probe.dt = dtype;
+    for (size_t i = 0; i < n_gates; ++i)
+        if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
+    std::string err;
+    const int rc = svk::plan_jit_check(n_qubits, dtype, gates, n_gates, !(flags & SV_NO_RELABEL),
+                                       n_programs, &err);
+    if (rc == -1) return fail(SV_EUNSUPPORTED, "%s", err.c_str());
+    if (rc != 0) return fail(SV_EDEVICE, "%s", err.c_str());
     return SV_OK;
 }
 
@@ -682,7 +775,7 @@ sv_status sv_plan_dense_inspect(int n_qubits, const sv_gate *gates, size_t n_gat
     probe.n = n_qubits;
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(&probe, gates[i], i)) return st;
-    if (sv_status st = reject_mcu(gates, n_gates)) return st;
+    if (sv_status st = reject_wide(gates, n_gates)) return st;
     const int nb = svk::plan_dense_inspect(n_qubits, gates, n_gates, block_masks, block_mats, cap);
     if (n_blocks) *n_blocks = nb;
     return SV_OK;
@@ -696,7 +789,6 @@ sv_status sv_plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_pl
     if (n_gates && !gates) return fail(SV_EINVAL, "null gate array");
     for (size_t i = 0; i < n_gates; ++i)
         if (sv_status st = validate_gate(s, gates[i], i)) return st;
-    if (sv_status st = reject_mcu(gates, n_gates)) return st;
     DeviceScope ds(s->device);
     std::string err;
     sv_status st = svk::plan_create(s, gates, n_gates, out, &err);

@@ -11,10 +11,20 @@
 // in registers, with one LDS exchange per group.
 #pragma once
 
+#ifdef __HIPCC_RTC__
+// Compiled at run time (jit.hip): the fixed-width integer types live in the
+// run-time compiler's own namespace.
+typedef __hip_internal::uint64_t uint64_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint8_t uint8_t;
+#else
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#endif
 
 namespace svk {
 
@@ -57,6 +67,14 @@ struct TileOp {
                        // area of thr, 2^(L-K) rows of K+1 values
     int32_t dout;      // TOP_DIAG: offset of the byte tables, or -1 (none)
     int32_t dbytes;    // TOP_DIAG: bytes of g the byte tables cover
+    // TOP_U / TOP_SWAP with several controls (a Toffoli gate has two): the op
+    // applies where every control is 1. lcm: the controls that are tile bits,
+    // as a mask of local tile bits (lctrl's bit included; pk is then -1);
+    // ocm: the controls outside the tile, as a mask of global index bits
+    // (octrl's bit included). Both 0 for ops with at most one control.
+    uint32_t lcm;
+    int32_t pad0;
+    uint64_t ocm;
     double m[8];       // 2x2 in FP64
     float mf[8];       // the same rounded to FP32 (complex64 states)
     double m4[32];     // TOP_U4: 4x4 in FP64, row major, (re, im); basis index
@@ -97,11 +115,13 @@ struct TileArgs {
                                    // (osrc >> 4 j) & 15
 };
 
+#ifndef __HIPCC_RTC__
 // Dynamic LDS of one work-group: padded tile plus the phase table.
 size_t tile_lds_bytes(bool c64, int L, bool diag);
 // Launches one pass: 2^(L-K) threads per work-group; each work-group walks
 // tiles g = blockIdx.x, blockIdx.x + gridDim.x, ... below 2^nnon.
 hipError_t launch_tile(const TileArgs &a, int K, bool c64, hipStream_t st);
+#endif
 
 // One task of a batched level launch: tiles [tile0, tile0 + ntiles) of pass
 // `pass` (an index into BatchArgs.passes) of circuit `circ`.
@@ -122,7 +142,9 @@ struct BatchArgs {
 
 // One level of a batch: 2^(L-4) threads per work-group (the largest tile of
 // the dtype), blocks_per_cu work-groups per CU taking tasks round-robin.
+#ifndef __HIPCC_RTC__
 hipError_t launch_level(const BatchArgs &b, bool c64, int blocks_per_cu, hipStream_t st);
+#endif
 
 // One circuit of a persistent launch: passes [pass0, pass0 + npass) of
 // PersistArgs.passes, all run in order by the one work-group that takes it.
@@ -141,6 +163,8 @@ struct PersistArgs {
     uint64_t *t_end;            // per circuit: when its last pass ended
     uint32_t count;
 };
+#ifndef __HIPCC_RTC__
 hipError_t launch_persist(const PersistArgs &p, bool c64, int blocks_per_cu, hipStream_t st);
+#endif
 
 }  // namespace svk

@@ -34,6 +34,8 @@ G_CU = 1       # 2x2 unitary on `target`, applied where bit `control` is 1
 G_CPHASE = 2   # diag(1, e^{i theta}) on `target`, controlled by `control`
 G_MCU = 3      # 2x2 unitary on `target`, applied where every control bit is 1;
                # the control mask's low 32 bits are in `control`, high 32 in `flags`
+G_UNITARY = 4  # 2^k x 2^k unitary on k = `control` qubits listed in 6-bit fields of
+               # `flags` (first qubit lowest); `target` indexes a side table of matrices
 
 GATE_DTYPE = np.dtype([
     ("kind", "<i4"), ("control", "<i4"), ("target", "<i4"), ("flags", "<i4"),
@@ -150,6 +152,39 @@ def gate_mcu(controls, target: int, m) -> np.ndarray:
     g["flags"] = np.array(mask >> 32, dtype=np.uint32).view(np.int32)
     g["m"][0] = m
     return g
+
+
+def gate_unitary(qubits, index: int) -> np.ndarray:
+    """A general gate on the listed qubits (k <= 5; qubits[0] is the least
+    significant bit of the local index) whose matrix is entry `index` of a
+    side table (see unitary_table)."""
+    qs = [int(q) for q in qubits]
+    if not 1 <= len(qs) <= 5:
+        raise ValueError("1 to 5 qubits")
+    packed = 0
+    for j, q in enumerate(qs):
+        packed |= q << (6 * j)
+    g = np.zeros(1, GATE_DTYPE)
+    g["kind"], g["control"], g["target"] = G_UNITARY, len(qs), int(index)
+    g["flags"] = np.array(packed, dtype=np.uint32).view(np.int32)
+    return g
+
+
+def unitary_qubits(g) -> list:
+    """The qubit list of a G_UNITARY record."""
+    packed = int(np.array(g["flags"], dtype=np.int32).view(np.uint32))
+    return [(packed >> (6 * j)) & 63 for j in range(int(g["control"]))]
+
+
+def unitary_table(mats) -> np.ndarray:
+    """Side table of G_UNITARY matrices: entry j holds matrix j (2^k x 2^k
+    complex) in its first 2 * 4^k doubles, row major, (re, im) interleaved;
+    every entry takes 2048 doubles."""
+    out = np.zeros((len(mats), 2048), dtype=np.float64)
+    for j, m in enumerate(mats):
+        v = np.ascontiguousarray(m, dtype=np.complex128).reshape(-1).view(np.float64)
+        out[j, :v.size] = v
+    return out
 
 
 def gate_control_mask(g) -> int:

@@ -323,8 +323,8 @@ def test_persist_rejects_bad_values():
 @pytest.mark.parametrize("flags", [sv.SV_FUSE, sv.SV_FUSE | sv.SV_GRAPH], ids=["direct", "graph"])
 def test_run_batch_one_call_mixed_states(flags):
     """sv_run_batch: complex64 and complex128 states of several sizes and
-    streams, a circuit with a Toffoli and one on 3 qubits (both run alone), an
-    empty circuit, a 24-qubit circuit (pass by pass on the batch's third
+    streams, a circuit with a Toffoli (batched), one on 3 qubits (run alone),
+    an empty circuit, a 24-qubit circuit (pass by pass on the batch's third
     stream); every result equals the circuit run alone with SV_FUSE."""
     import torch
     side = torch.cuda.Stream()

@@ -14,7 +14,9 @@ import pytest
 import oracle
 import paper_1801_01037_amd as sv
 import qcircuits as qc
-from tests.gpu_helpers import DTYPE_IDS, DTYPES, assert_close, rounded, state_from_host
+from tests.gpu_helpers import DTYPE_IDS, DTYPES, STREAMING, STREAMING_IDS, assert_close
+from tests.gpu_helpers import oracle_threads, rounded, state_from_host
+from tests.test_plan import mixed_circuit
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +66,9 @@ def test_mcu_matches_oracle(dtype):
 @pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
 @pytest.mark.parametrize("flags", [0, sv.SV_FUSE, sv.SV_FUSE_DENSE], ids=["pergate", "fuse", "dense"])
 def test_circuit_with_toffolis_matches_oracle(dtype, flags):
-    """Records of several-control gates inside a circuit run between the
-    planned segments of the other gates, in list order."""
+    """Records of several-control gates inside a circuit: in tile passes with
+    the other gates (SV_FUSE), in dense blocks when they span at most five
+    qubits (the last one, of five, does), gate by gate otherwise."""
     n = 14
     parts = [qc.layer_circuit(n, 3, 5)]
     for k in range(6):
@@ -110,12 +113,74 @@ def test_mcu_rejects_bad_masks():
             with pytest.raises(sv.SVError) as e:
                 sv.sv_apply_mcu(h, controls, t, qc.X_MATRIX)
             assert e.value.status == sv.SV_EINVAL
-        g = qc.gate_mcu((0, 1), 2, qc.X_MATRIX)
-        p_err = None
-        try:
-            sv.sv_plan_create(h, g)
-        except sv.SVError as e:
-            p_err = e.status
-        assert p_err == sv.SV_EUNSUPPORTED
     finally:
         sv.sv_destroy(h)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
+@pytest.mark.parametrize("n", [3, 4, 6, 12, 13, 17, 20])
+def test_several_controls_inside_fused_passes(dtype, n):
+    """Mixed circuits with Toffolis and gates of up to four controls, fused:
+    controls on register bits, on other tile bits and outside the tile, in
+    relabelled and standard storage order, against the oracle."""
+    g = mixed_circuit(n, 400, 13 * n + 2, mcu=True)
+    psi0 = rounded(qc.random_state(n, 310 + n), dtype)
+    ref = psi0.copy()
+    oracle.run_circuit(ref, g)
+    for flags in (sv.SV_FUSE, sv.SV_FUSE | sv.SV_NO_RELABEL, sv.SV_FUSE_DENSE):
+        h = state_from_host(n, dtype, psi0)
+        try:
+            sv.sv_run_circuit(h, g, flags)
+            got = sv.sv_copy_out(h)
+        finally:
+            sv.sv_destroy(h)
+        assert_close(got, ref, dtype, len(g), f"n={n} flags={flags}")
+
+
+@pytest.mark.parametrize("n,dtype", STREAMING, ids=STREAMING_IDS)
+def test_several_controls_inside_fused_passes_streaming_sizes(n, dtype):
+    g = mixed_circuit(n, 300, 17 * n, mcu=True)
+    psi0 = rounded(qc.random_state(n, 320 + n), dtype)
+    ref = psi0.copy()
+    with oracle_threads():
+        oracle.run_circuit(ref, g)
+    h = state_from_host(n, dtype, psi0)
+    try:
+        sv.sv_run_circuit(h, g, sv.SV_FUSE)
+        got = sv.sv_copy_out(h)
+    finally:
+        sv.sv_destroy(h)
+    assert_close(got, ref, dtype, len(g), f"n={n}")
+
+
+def test_toffoli_circuits_batched():
+    """Plans hold several-control gates, so circuits with Toffolis run in a
+    batch (persistent launch, levels and the third stream) and give the
+    bits of the circuit run alone."""
+    dtype = sv.SV_C64
+    specs = [(10, 1), (12, 2), (14, 3), (16, 4), (18, 5)]
+    circuits = [np.concatenate([mixed_circuit(n, 200, s, mcu=True), qc.layer_circuit(n, 3, s)])
+                for n, s in specs]
+    states = [sv.sv_create(n, dtype) for n, _ in specs]
+    plans = [sv.sv_plan_create(h, g) for h, g in zip(states, circuits)]
+    b = sv.sv_batch_create(dtype)
+    try:
+        sv.sv_batch_persist(b, 4)
+        sv.sv_batch_solo(b, 64)
+        sv.sv_batch_run(b, plans, flags=sv.SV_GRAPH)
+        outs = [sv.sv_copy_out(h) for h in states]
+    finally:
+        sv.sv_batch_destroy(b)
+        for p in plans:
+            sv.sv_plan_destroy(p)
+        for h in states:
+            sv.sv_destroy(h)
+    for (n, _), g, got in zip(specs, circuits, outs):
+        h = sv.sv_create(n, dtype)
+        try:
+            sv.sv_run_circuit(h, g, sv.SV_FUSE)
+            want = sv.sv_copy_out(h)
+        finally:
+            sv.sv_destroy(h)
+        assert np.array_equal(got, want), n
+        assert_close(got, oracle.simulate(n, g), dtype, len(g), f"batch n={n}")

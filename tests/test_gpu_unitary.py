@@ -113,3 +113,66 @@ def test_unitary_rejects_bad_arguments():
         assert e.value.status == sv.SV_EINVAL
     finally:
         sv.sv_destroy(h)
+
+
+def _general_circuit(n, seed):
+    """Layers, a Toffoli and general gates on k = 1..5 qubits (list order
+    mixed, low and high qubits), with their side table."""
+    ks = [2, 3, 5, 1, 4, 2]
+    mats = [qc.random_unitary(k, seed + 10 * k + j) for j, k in enumerate(ks)]
+    rng = np.random.default_rng(seed)
+    parts = [qc.layer_circuit(n, 2, seed)]
+    for j, k in enumerate(ks):
+        qs = rng.choice(n, size=k, replace=False)
+        parts.append(qc.gate_unitary(qs, j))
+        parts.append(qc.layer_circuit(n, 1, seed + j + 1))
+    parts.append(qc.gate_mcu((0, n - 1), 1, qc.X_MATRIX))
+    parts.append(qc.gate_unitary(list(range(n - 5, n)), 2))
+    return np.concatenate(parts), qc.unitary_table(mats)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
+@pytest.mark.parametrize("n", [6, 10, 16])
+def test_circuits_with_general_gates(dtype, n):
+    """SV_G_UNITARY records inside circuits (sv_run_circuit_ex): gate by gate,
+    fused (generic and compiled passes) and dense, against the oracle."""
+    g, tab = _general_circuit(n, 50 + n)
+    psi0 = rounded(qc.random_state(n, 60 + n), dtype)
+    ref = psi0.copy()
+    oracle.run_circuit(ref, g, tab)
+    # G: the gates applied, a general gate counting its 2^k terms
+    G = int(sum(1 << int(x["control"]) if int(x["kind"]) == qc.G_UNITARY else 1 for x in g))
+    for flags in (0, sv.SV_FUSE, sv.SV_FUSE | sv.SV_JIT, sv.SV_FUSE_DENSE):
+        h = state_from_host(n, dtype, psi0)
+        try:
+            sv.sv_run_circuit(h, g, flags, tab)
+            got = sv.sv_copy_out(h)
+        finally:
+            sv.sv_destroy(h)
+        assert_close(got, ref, dtype, G, f"n={n} flags={flags}")
+
+
+def test_general_gate_records_are_checked():
+    n = 8
+    g, tab = _general_circuit(n, 3)
+    h = sv.sv_create(n, sv.SV_C128)
+    try:
+        sv.sv_reset(h, 9)
+        before = sv.sv_copy_out(h)
+        bad = [g.copy() for _ in range(3)]
+        bad[0][len(g) // 2] = qc.gate_unitary([1, 1], 0)[0]      # a qubit twice
+        bad[1][len(g) // 2] = qc.gate_unitary([1, 2], 99)[0]     # matrix index past the table
+        bad[2][len(g) // 2] = qc.gate_unitary([1, 8], 0)[0]      # qubit outside the register
+        for b in bad:
+            with pytest.raises(sv.SVError) as e:
+                sv.sv_run_circuit(h, b, sv.SV_FUSE, tab)
+            assert e.value.status == sv.SV_EINVAL
+        with pytest.raises(sv.SVError) as e:                     # no table at all
+            sv.sv_run_circuit(h, g, sv.SV_FUSE)
+        assert e.value.status == sv.SV_EINVAL
+        with pytest.raises(sv.SVError) as e:
+            sv.sv_run_circuit(h, g, sv.SV_FUSE | sv.SV_GRAPH, tab)
+        assert e.value.status == sv.SV_EUNSUPPORTED
+        assert np.array_equal(sv.sv_copy_out(h), before)          # nothing ran
+    finally:
+        sv.sv_destroy(h)

@@ -452,3 +452,27 @@ def test_sampling_frequencies_follow_the_probabilities():
     psi2[[2, 5, 9]] = [0.6, 0.0, 0.8]
     got = oracle.sample_indices(psi2, np.array([0.0, 0.35, 0.37, 0.999999, np.nextafter(1.0, 0.0)]))
     assert list(got) == [2, 2, 9, 9, 9]
+
+
+def test_general_gate_records_follow_the_dense_tier():
+    """Records of general gates (kind 4, matrices from a side table) are
+    applied in list order among the other records: the stride tier equals
+    the dense Kronecker tier on a circuit where they do not commute with
+    their neighbours."""
+    from oracle import dense
+    n = 7
+    mats = [qc.random_unitary(k, 20 + k) for k in (2, 3, 5, 1)]
+    tab = qc.unitary_table(mats)
+    g = np.concatenate([qc.layer_circuit(n, 2, 1), qc.gate_unitary([3, 0], 0),
+                        qc.layer_circuit(n, 1, 2), qc.gate_unitary([6, 2, 4], 1),
+                        qc.gate_unitary([1, 5, 0, 6, 3], 2), qc.gate_unitary([4], 3),
+                        qc.gate_cnot(4, 5), qc.gate_unitary([5, 4], 0)])
+    psi0 = qc.random_state(n, 8)
+    a = psi0.copy()
+    oracle.run_circuit(a, g, tab)
+    b = dense.run_circuit(n, g, psi0, tab)
+    assert np.max(np.abs(a - b)) <= 1e-13
+    # the same gates in another order give another state
+    c = psi0.copy()
+    oracle.run_circuit(c, g[::-1].copy(), tab)
+    assert np.max(np.abs(a - c)) > 1e-3

@@ -20,6 +20,9 @@ def _is_diag(g):
 
 
 def _qubits(g):
+    if int(g["kind"]) == qc.G_MCU:
+        m = qc.gate_control_mask(g)
+        return {int(g["target"])} | {q for q in range(64) if (m >> q) & 1}
     return {int(g["target"])} | ({int(g["control"])} if int(g["control"]) >= 0 else set())
 
 
@@ -54,12 +57,22 @@ def no_fusion(monkeypatch):
     monkeypatch.setenv("SV_TILE_FUSE4", "0")
 
 
-def mixed_circuit(n, count, seed):
+def mixed_circuit(n, count, seed, mcu=False):
+    """Random gates of every kind a pass holds: 2x2, controlled 2x2, CNOT,
+    controlled phase, one-qubit phase, X; with `mcu` (n >= 3) also gates with
+    two to four controls (Toffoli among them)."""
     rng = np.random.default_rng(seed)
     su2 = qc.haar_su2(seed, count)
     out = []
+    kinds = 8 if (mcu and n >= 3) else 6
     for i in range(count):
-        kind = int(rng.integers(0, 6)) if n > 1 else 0
+        kind = int(rng.integers(0, kinds)) if n > 1 else 0
+        if kind >= 6:
+            t = int(rng.integers(0, n))
+            k = int(rng.integers(2, min(4, n - 1) + 1))
+            ctrls = rng.choice([q for q in range(n) if q != t], size=k, replace=False)
+            out.append(qc.gate_mcu(ctrls, t, qc.X_MATRIX if kind == 6 else su2[i]))
+            continue
         t = int(rng.integers(0, n))
         c = int(rng.integers(0, n - 1)) if n > 1 else 0
         c = c + 1 if c >= t else c
@@ -121,18 +134,44 @@ def test_plan_rejects_bad_gates():
         sv.sv_plan_inspect(4, sv.SV_C128, qc.gate_u(4, qc.X_MATRIX))
 
 
-def test_plans_reject_gates_with_several_controls():
-    toffoli = qc.gate_mcu((0, 1), 2, qc.X_MATRIX)
-    with pytest.raises(sv.SVError) as e:
-        sv.sv_plan_inspect(6, sv.SV_C128, np.concatenate([qc.gate_u(0, qc.H_MATRIX), toffoli]))
-    assert e.value.status == sv.SV_EUNSUPPORTED
-    # malformed masks are argument errors: the target among the controls, a
-    # control at or above n, no control at all
+@pytest.mark.parametrize("n", [3, 4, 9, 13, 22])
+def test_plans_hold_gates_with_several_controls(n):
+    """Toffoli and other several-control gates join tile passes: every gate is
+    placed once and gates sharing a qubit keep their order, in both storage
+    orders."""
+    for seed in range(3):
+        g = mixed_circuit(n, 300, seed + 31 * n, mcu=True)
+        assert (g["kind"] == qc.G_MCU).sum() > 10
+        for dtype in (sv.SV_C128, sv.SV_C64):
+            check_plan_order(n, dtype, g)
+            sv.sv_plan_inspect(n, dtype, g, sv.SV_FUSE | sv.SV_NO_RELABEL)
+
+
+def test_several_control_plans_keep_every_order(no_fusion):
+    g = mixed_circuit(14, 400, 5, mcu=True)
+    check_plan_order(14, sv.SV_C128, g, strict=True)
+
+
+def test_malformed_control_masks_are_rejected():
+    # the target among the controls, a control at or above n, no control at all
     for bad in (qc.gate_mcu((0, 2), 2, qc.X_MATRIX), qc.gate_mcu((0, 6), 2, qc.X_MATRIX),
                 qc.gate_mcu((), 2, qc.X_MATRIX)):
         with pytest.raises(sv.SVError) as e:
             sv.sv_plan_inspect(6, sv.SV_C128, bad)
         assert e.value.status == sv.SV_EINVAL
+
+
+def test_dense_plans_take_gates_of_up_to_five_qubits():
+    four = qc.gate_mcu((0, 3, 5, 7), 9, qc.X_MATRIX)    # five qubits: one block
+    five = qc.gate_mcu((0, 3, 5, 7, 8), 9, qc.X_MATRIX)  # six: too wide
+    masks, mats = sv.sv_plan_dense_inspect(12, four)
+    assert len(masks) == 1 and int(masks[0]) == 0b1010101001
+    # the block is the four-control X: an exchange of the two columns whose
+    # four control bits are set, identity elsewhere
+    assert np.allclose(np.abs(mats[0]) ** 2 @ np.ones(32), 1.0)
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_dense_inspect(12, five, cap=4)
+    assert e.value.status == sv.SV_EUNSUPPORTED
 
 
 # ---- relabelling between passes (non-sequential storage) ---------------------
@@ -193,3 +232,22 @@ def test_benchmark_plans_do_not_grow(dtype, shape):
         _, passes, groups, ops = sv.sv_plan_inspect(30, dtype, g, sv.SV_FUSE)
         p0, g0, o0 = shape[name]
         assert passes <= p0 and groups <= g0 and ops <= o0, (name, passes, groups, ops)
+
+
+# ---- passes compiled at run time (SV_JIT) ------------------------------------
+
+def test_pass_programs_compile_on_the_host():
+    """The programs SV_FUSE | SV_JIT writes for a plan compile with hipRTC
+    without a device: layered passes (one program per distinct pass shape),
+    several-control gates, diagonal ops (the QFT), both storage orders, both
+    precisions."""
+    g = np.concatenate([qc.layer_circuit(14, 6, 3), mixed_circuit(14, 60, 4, mcu=True)])
+    for dtype in (sv.SV_C128, sv.SV_C64):
+        k = sv.sv_plan_jit_check(14, dtype, g)
+        assert 1 <= k <= sv.sv_plan_inspect(14, dtype, g)[1]
+        assert sv.sv_plan_jit_check(14, dtype, g, sv.SV_FUSE | sv.SV_JIT | sv.SV_NO_RELABEL) >= 1
+    assert sv.sv_plan_jit_check(12, sv.SV_C128, qc.qft_circuit(12)) >= 1
+    assert sv.sv_plan_jit_check(16, sv.SV_C64, qc.workload_layers_qft(16, 4, 1)) >= 1
+    with pytest.raises(sv.SVError) as e:
+        sv.sv_plan_jit_check(6, sv.SV_C128, g[:4], sv.SV_FUSE)
+    assert e.value.status == sv.SV_EINVAL
