@@ -10,9 +10,10 @@ them together:
     circuit fused into tile passes, uploaded once);
   * step: every active circuit of a dtype advances by up to `chunk` passes
     in one batched launch sequence (sv_batch_run); complex64 and complex128
-    batches run on their own streams and overlap on the device;
-  * while a step runs, newly arrived requests are admitted and planned on
-    the host, and they join at the next step; finished circuits leave and
+    batches run on their own streams and overlap on the device, and each
+    dtype starts its next step as soon as its own step has finished;
+  * while steps run, newly arrived requests are admitted and planned on the
+    host, and they join their dtype's next step; finished circuits leave and
     free their memory.
 
 Latency of a request = completion time - arrival time (host clock). The
@@ -130,43 +131,59 @@ class Server:
                 self._admit(r, clock())
                 active[r.dtype].append(r)
 
-        while pending or waiting or active[sv.SV_C64] or active[sv.SV_C128]:
+        # Each dtype steps on its own stream, independently: when a dtype's
+        # step has finished on the device, its circuits are retired and its
+        # next step is launched at once (with the requests admitted
+        # meanwhile), whether or not the other dtype's step is still running.
+        inflight = {sv.SV_C64: None, sv.SV_C128: None}   # (event, circuits, pass counts)
+
+        def retire(dt):
+            ev, rs, count = inflight[dt]
+            inflight[dt] = None
+            finished = set()
+            for r, c in zip(rs, count):
+                r.next_pass += c
+                if r.next_pass >= r.passes:
+                    r.t_done = clock()
+                    self._release(r)
+                    done.append(r)
+                    finished.add(id(r))
+            active[dt] = [r for r in active[dt] if id(r) not in finished]
+
+        def launch(dt):
+            rs = list(active[dt])
+            plans = [r.plan for r in rs]
+            first = [r.next_pass for r in rs]
+            count = [min(self.chunk, r.passes - r.next_pass) for r in rs]
+            self.streams[dt].wait_stream(torch.cuda.current_stream())
+            sv.sv_batch_run(self.batches[dt], plans, first, count)
+            ev = torch.cuda.Event()
+            ev.record(self.streams[dt])
+            inflight[dt] = (ev, rs, count)
+
+        dtypes = (sv.SV_C64, sv.SV_C128)
+        while pending or waiting or any(active.values()) or any(inflight.values()):
             admit_arrived()
-            if not (active[sv.SV_C64] or active[sv.SV_C128]):
+            progressed = False
+            for dt in dtypes:
+                if inflight[dt] is not None:
+                    if not inflight[dt][0].query():
+                        continue
+                    retire(dt)
+                    progressed = True
+                if active[dt]:
+                    launch(dt)
+                    steps += 1
+                    progressed = True
+            if progressed:
+                continue
+            if not any(inflight.values()):
+                # nothing on the device: wait for the next arrival
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - clock()))
                 continue
-            # One step: every active circuit advances by up to `chunk` passes.
-            launched = []
-            for dt in (sv.SV_C64, sv.SV_C128):
-                rs = list(active[dt])          # the circuits of this step
-                if not rs:
-                    continue
-                plans = [r.plan for r in rs]
-                first = [r.next_pass for r in rs]
-                count = [min(self.chunk, r.passes - r.next_pass) for r in rs]
-                self.streams[dt].wait_stream(torch.cuda.current_stream())
-                sv.sv_batch_run(self.batches[dt], plans, first, count)
-                launched.append((dt, rs, count))
-            steps += 1
-            # Host work overlapped with the step: admit and plan new arrivals
-            # (they are ordered after the step on their dtype's stream).
-            admit_arrived()
-            for dt, rs, count in launched:
-                self.streams[dt].synchronize()
-                keep = []
-                for r, c in zip(rs, count):
-                    r.next_pass += c
-                    if r.next_pass >= r.passes:
-                        r.t_done = clock()
-                        self._release(r)
-                        done.append(r)
-                    else:
-                        keep.append(r)
-                # requests admitted during the step stay for the next one
-                stepped = {id(r) for r in rs}
-                keep += [r for r in active[dt] if id(r) not in stepped]
-                active[dt] = keep
+            # Steps in flight: admit arrivals meanwhile, check again shortly.
+            time.sleep(2e-4)
         elapsed = clock()
         lat = np.array([r.latency for r in done])
         gates = int(sum(len(r.gates) for r in done))
