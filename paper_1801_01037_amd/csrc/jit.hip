@@ -15,6 +15,14 @@
 // compiled program serves every pass of the same shape; kernels are cached per
 // device and program text for the life of the process.
 //
+// What is known when a program is written out is also used to do less work:
+// a diagonal op skips the phases that its shape makes exactly 1 (a controlled
+// phase on a register bit touches half of the amplitudes), a real 2x2 (a
+// Hadamard) skips its zero imaginary parts, and the first and last groups
+// move the tile between HBM and registers directly, without an LDS round
+// trip, when their register bits leave the tile's low index bits to the
+// threads. None of this changes a result bit.
+//
 // A compiled program that would spill registers to scratch memory is not
 // used: its pass runs with the generic kernel.
 #include <hip/hiprtc.h>
@@ -50,6 +58,37 @@ int env_int(const char *name, int dflt)
 const int kJitWavesC128 = env_int("SV_JIT_WAVES128", 2);
 const int kJitWavesC64 = env_int("SV_JIT_WAVES64", 4);
 
+// Output local bit that input local bit s is written to: the pass's
+// relabelled order when it has one.
+int out_bit(const TileArgs &a, int s)
+{
+    if (a.permute)
+        for (int j = 0; j < a.L; ++j)
+            if (int((a.osrc >> (4 * j)) & 15u) == s) return j;
+    return s;
+}
+
+// The first group loads its registers straight from HBM when the threads'
+// own bits hold the tile's low nlow bits (then 2^nlow neighbouring threads
+// read one aligned run of amplitudes); the last group stores straight to HBM
+// when the same holds for the bits it writes to.
+bool direct_first(const TileArgs &a, const TileGroup &G, int K)
+{
+    for (int k = 0; k < K; ++k)
+        if (G.s[k] < a.nlow) return false;
+    return true;
+}
+
+bool direct_last(const TileArgs &a, const TileGroup &G, int K)
+{
+    for (int k = 0; k < a.nlow && k < a.L - K; ++k)
+        if (out_bit(a, G.ns[k]) >= a.nlow) return false;
+    return true;
+}
+
+const bool kJitDirect = env_int("SV_JIT_DIRECT", 1) != 0;
+
+
 std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp *ops, int K,
                         bool c64, bool nt)
 {
@@ -57,6 +96,10 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
     const uint32_t size = 1u << L;
     const uint32_t slots = c64 ? size + (size >> 5) : size + (size >> 4);
     const int threads = 1 << (L - K);
+    const int NR = 1 << K;
+    const int ng = a.ngroups;
+    const bool df = kJitDirect && ng > 0 && direct_first(a, groups[0], K);
+    const bool dl = kJitDirect && ng > 0 && direct_last(a, groups[ng - 1], K);
     std::ostringstream o;
     // Resident waves per SIMD the code is built for: the LDS of a work-group
     // allows two complex128 tiles per CU (two waves per SIMD); complex64
@@ -76,28 +119,63 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
       << "    A *tab = smem + " << slots << ";\n"
       << "    CGroup *groups = (CGroup *)(a.groups) + a.group0;\n";
     // A pass that only restores the storage order has no group (and no op).
-    const int op_base = a.ngroups > 0 ? groups[0].op0 : 0;
-    if (a.ngroups > 0) o << "    COp *ops = (COp *)(a.ops) + groups[0].op0;\n";
+    const int op_base = ng > 0 ? groups[0].op0 : 0;
+    if (ng > 0) o << "    COp *ops = (COp *)(a.ops) + groups[0].op0;\n";
+    // Direct transfers: each thread's own index bits (the same for every
+    // tile) and the index bits of the register bits, computed once.
+    if (df || dl) o << "    const uint32_t t0 = threadIdx.x;\n";
+    if (df) {
+        const TileGroup &G = groups[0];
+        o << "    const uint64_t dfirst = deposit(0u";
+        for (int k = 0; k < L - K; ++k) o << " | (((t0 >> " << k << ") & 1u) << " << G.ns[k] << ")";
+        o << ", a.tmask);\n    const uint64_t rbf[K] = {";
+        for (int k = 0; k < K; ++k) o << (k ? ", " : "") << "nth_bit(a.tmask, " << G.s[k] << ")";
+        o << "};\n";
+    }
+    if (dl) {
+        const TileGroup &G = groups[ng - 1];
+        o << "    const uint64_t dlast = deposit(0u";
+        for (int k = 0; k < L - K; ++k)
+            o << " | (((t0 >> " << k << ") & 1u) << " << out_bit(a, G.ns[k]) << ")";
+        o << ", a.tmask);\n    const uint64_t obl[K] = {";
+        for (int k = 0; k < K; ++k) o << (k ? ", " : "") << "nth_bit(a.tmask, " << out_bit(a, G.s[k]) << ")";
+        o << "};\n    const uint32_t xrl[1 << K] = {";
+        for (int r = 0; r < NR; ++r) {
+            uint32_t x = uint32_t(r);
+            if (G.has_exit) {
+                x = G.xb;
+                for (int k = 0; k < K; ++k)
+                    if (r & (1 << k)) x ^= G.xs[k];
+            }
+            o << (r ? ", " : "") << x << "u";
+        }
+        o << "};\n";
+    }
     // tid is made opaque at every group, so that nothing derived from it (slot
     // addresses, per-thread diagonal rows) is hoisted out of the tile loop
-    // and held in registers through all the tiles.
+    // and held in registers through all the tiles. Every thread of the
+    // work-group holds amplitudes (2^(L-K) threads).
     o << "    auto prog = [&](uint64_t g, uint64_t gbase, const Walk<K> &w) {\n";
-    for (int gi = 0; gi < a.ngroups; ++gi) {
+    for (int gi = 0; gi < ng; ++gi) {
         const TileGroup &G = groups[gi];
+        const bool first = gi == 0 && df, last = gi == ng - 1 && dl;
         o << "        {\n"
           << "            CGroup &G = groups[" << gi << "];\n"
           << "            uint32_t tid = w.tid;\n"
           << "            asm volatile(\"\" : \"+v\"(tid));\n"
           << "            __builtin_amdgcn_s_setprio(2);\n"
-          << "            if (w.active) {\n"
-          << "                const uint32_t lbase = 0u";
+          << "            const uint32_t lbase = 0u";
         for (int k = 0; k < L - K; ++k) o << " | (((tid >> " << k << ") & 1u) << " << G.ns[k] << ")";
-        o << ";\n                const uint32_t soff[K] = {";
+        o << ";\n            const uint32_t soff[K] = {";
         for (int k = 0; k < K; ++k) o << (k ? ", " : "") << (1u << G.s[k]) << "u";
         o << "};\n"
-          << "                uint32_t li[1 << K];\n"
-          << "                A v[1 << K], u[1 << K];\n"
-          << "                gather<C64, K>(lds, lbase, soff, li, v);\n";
+          << "            uint32_t li[1 << K];\n"
+          << "            A v[1 << K], u[1 << K];\n";
+        if (first)
+            o << "            load_direct<C64, K, " << (nt ? "true" : "false")
+              << ">(a, gbase | dfirst, rbf, lbase, soff, li, v);\n";
+        else
+            o << "            gather<C64, K>(lds, lbase, soff, li, v);\n";
         const char *arr[2] = {"v", "u"};
         for (int oi = 0; oi < G.nops; ++oi) {
             const TileOp &t = ops[G.op0 + oi];
@@ -111,9 +189,14 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
                 // registers each). Tying the thread index to all of the op's
                 // input amplitudes makes it evaluate them when the op runs.
                 core << "{ uint32_t dtid = tid; asm volatile(\"\" : \"+v\"(dtid) :";
-                for (int r = 0; r < (1 << K); ++r) core << (r ? ", " : " ") << "\"v\"(" << in << "[" << r << "].x)";
-                core << "); apply_diag<C64, K>(" << in << ", " << out << ", ops[" << k
-                     << "], a.dtab, a.L, G, g, dtid, tab); }";
+                for (int r = 0; r < NR; ++r) core << (r ? ", " : " ") << "\"v\"(" << in << "[" << r << "].x)";
+                // The op's shape: phases that are exactly 1 are skipped.
+                uint32_t one = 0;
+                for (int r = 0; r < NR; ++r)
+                    if (!t.pj || (t.m4[2 * r] == 1.0 && t.m4[2 * r + 1] == 0.0)) one |= 1u << r;
+                core << "); apply_diag_shape<C64, K, " << (t.dlin & ((1u << K) - 1)) << "u, "
+                     << ((t.dlin & kDiagBase) ? "true" : "false") << ", " << one << "u>(" << in
+                     << ", " << out << ", ops[" << k << "], a.dtab, a.L, G, g, dtid, tab); }";
             } else if (t.kind == TOP_U4) {
                 core << "u4_pp<C64, K, " << t.pj << ", " << t.pk << ">(" << in << ", " << out
                      << ", ops[" << k << "]);";
@@ -122,10 +205,14 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
                 if (t.pk >= 0)
                     core << "pair_rc<C64, K, " << t.pj << ", " << t.pk << ", " << sw << ">(" << in
                          << ", " << out << ", ops[" << k << "]);";
-                else
+                else {
+                    const bool real = t.kind == TOP_U && t.m[1] == 0.0 && t.m[3] == 0.0 &&
+                                      t.m[5] == 0.0 && t.m[7] == 0.0;
                     core << "pair_pj<C64, K, " << t.pj << ", " << sw << ", "
-                         << ((t.lctrl >= 0 || t.lcm) ? "true" : "false") << ">(" << in << ", "
-                         << out << ", li, ops[" << k << "]);";
+                         << ((t.lctrl >= 0 || t.lcm) ? "true" : "false") << ", "
+                         << (real ? "true" : "false") << ">(" << in << ", " << out << ", li, ops["
+                         << k << "]);";
+                }
             }
             std::string cond;
             if (t.kind != TOP_DIAG && t.kind != TOP_U4) {
@@ -136,21 +223,45 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
                 }
             }
             if (cond.empty())
-                o << "                " << core.str() << "\n";
+                o << "            " << core.str() << "\n";
             else
-                o << "                if (" << cond << ") " << core.str() << "\n"
-                  << "                else copy_amps<C64, K>(" << in << ", " << out << ");\n";
+                o << "            if (" << cond << ") " << core.str() << "\n"
+                  << "            else copy_amps<C64, K>(" << in << ", " << out << ");\n";
         }
-        o << "                scatter<C64, K>(lds, " << arr[G.nops & 1]
-          << ", li, lbase, soff, G, " << (G.has_exit ? "true" : "false") << ");\n"
-          << "            }\n"
+        const char *fin = arr[G.nops & 1];
+        if (last) {
+            if (first) {
+                // One group, loaded and stored directly: every load of the
+                // tile has returned before a store may overwrite its
+                // amplitude (a relabelled store writes other threads' ones,
+                // so the whole work-group waits).
+                o << "            asm volatile(\"\" : :";
+                for (int r = 0; r < NR; ++r) o << (r ? ", " : " ") << "\"v\"(v[" << r << "].x)";
+                o << ");\n";
+                if (a.permute) o << "            lds_barrier();\n";
+            }
+            o << "            store_direct<C64, K, " << (nt ? "true" : "false")
+              << ">(a, gbase | dlast, obl, xrl, " << fin << ");\n"
+              << "            __builtin_amdgcn_s_setprio(0);\n"
+              << "        }\n";
+            continue;
+        }
+        // A first group that loaded from HBM writes slots that other threads
+        // of the previous tile may still be reading.
+        if (first) o << "            lds_barrier();\n";
+        o << "            scatter<C64, K>(lds, " << fin << ", li, lbase, soff, G, "
+          << (G.has_exit ? "true" : "false") << ");\n"
           << "            __builtin_amdgcn_s_setprio(0);\n"
           << "            lds_barrier();\n"
           << "        }\n";
     }
     o << "    };\n"
-      << "    walk_tiles<C64, K, " << (nt ? "true" : "false")
+      << "    walk_tiles<C64, K, " << (nt ? "true" : "false") << ", " << (df ? "true" : "false")
+      << ", " << (dl ? "true" : "false")
       << ">(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab, prog);\n}\n";
+    if (std::getenv("SV_JIT_VERBOSE"))
+        std::fprintf(stderr, "[sv jit] pass: %d groups, direct first %d, direct last %d, permute %d\n",
+                     ng, int(df), int(dl), int(a.permute));
     return o.str();
 }
 
@@ -275,8 +386,13 @@ sv_status jit_passes(sv_dtype dt, int K, const std::vector<TileArgs> &passes,
         if (e == hipSuccess) e = hipModuleGetFunction(&c.fn, c.mod, "svj_pass");
         int scratch = 0;
         if (e == hipSuccess &&
-            hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, c.fn) == hipSuccess &&
-            scratch > 0) {
+            hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, c.fn) != hipSuccess)
+            scratch = 0;
+        if (std::getenv("SV_JIT_VERBOSE"))
+            std::fprintf(stderr, "[sv jit] program %zu: %zu bytes of code, load %s, scratch %d bytes\n",
+                         std::hash<std::string>{}(todo[i]), codes[i].size(), hipGetErrorString(e),
+                         scratch);
+        if (e == hipSuccess && scratch > 0) {
             // spills registers: the generic kernel runs such passes
             (void)hipModuleUnload(c.mod);
             c = Compiled{};

@@ -850,6 +850,22 @@ bool diag_tables(const POp &op, const std::vector<int> &T, const std::vector<int
     }
     to.pj = any ? 1 : 0;
     const int nt = L - K;
+    // The shape of the op: which coef_k, and whether base, can be non-zero
+    // (their terms, as set up above: the thread rows below and the byte
+    // tables of the outside weights).
+    auto nonzero = [](const std::vector<uint64_t> &v) {
+        return std::any_of(v.begin(), v.end(), [](uint64_t t) { return t != 0; });
+    };
+    to.dlin = nonzero(ow[L]) ? kDiagBase : 0u;
+    for (int k = 0; k < nt; ++k) {
+        if (a[ns[k]] || nonzero(ow[ns[k]])) to.dlin |= kDiagBase;
+        for (int k2 = k + 1; k2 < nt; ++k2)
+            if (q(ns[k], ns[k2])) to.dlin |= kDiagBase;
+        for (int j = 0; j < K; ++j)
+            if (q(ns[k], S[j])) to.dlin |= 1u << j;
+    }
+    for (int j = 0; j < K; ++j)
+        if (nonzero(ow[S[j]])) to.dlin |= 1u << j;
     to.dthr = int(dtab.size());
     for (uint32_t tid = 0; tid < (1u << nt); ++tid) {
         uint64_t b0 = 0, cr[kTileMaxK] = {};

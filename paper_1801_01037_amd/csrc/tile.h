@@ -35,6 +35,7 @@ constexpr int kTileL64 = 12, kTileK64 = 4;     // 32 KiB of complex64 per tile, 
 constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
 
 enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2, TOP_U4 = 3 };
+constexpr uint32_t kDiagBase = 1u << 31;   // TileOp.dlin: base can be non-zero
 
 // A diagonal op multiplies each amplitude by e^{2 pi i T / 2^64}, where T is
 // an exact uint64 sum (mod one full turn): a quadratic form in the index bits,
@@ -73,7 +74,10 @@ struct TileOp {
     // ocm: the controls outside the tile, as a mask of global index bits
     // (octrl's bit included). Both 0 for ops with at most one control.
     uint32_t lcm;
-    int32_t pad0;
+    // TOP_DIAG: bit k (k < K) set when coef_k can be non-zero for some thread
+    // or tile, kDiagBase when base can; the others are zero for every
+    // amplitude (a pass compiled for its program skips their phases).
+    uint32_t dlin;
     uint64_t ocm;
     double m[8];       // 2x2 in FP64
     float mf[8];       // the same rounded to FP32 (complex64 states)

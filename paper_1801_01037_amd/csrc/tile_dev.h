@@ -62,12 +62,23 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask)
     return out;
 }
 
+template <typename R>
+__device__ __forceinline__ R fmadd(R a, R b, R c)
+{
+    if constexpr (std::is_same_v<R, float>) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// Complex product with its roundings fixed: in each component one product is
+// rounded and the other enters a fused multiply-add. Left to the compiler,
+// which product is rounded depends on the surrounding code, and two kernels
+// applying the same op could differ in the last bit.
 template <typename A>
 __device__ __forceinline__ A cmul(A x, A y)
 {
     A r;
-    r.x = x.x * y.x - x.y * y.y;
-    r.y = x.x * y.y + x.y * y.x;
+    r.x = fmadd(x.x, y.x, -(x.y * y.y));
+    r.y = fmadd(x.x, y.y, x.y * y.x);
     return r;
 }
 
@@ -95,12 +106,6 @@ __device__ __forceinline__ AmpT<C64> turn_phase(uint64_t T, const AmpT<C64> *tab
     return cmul(cmul(e1, e2), e3);
 }
 
-template <typename R>
-__device__ __forceinline__ R fmadd(R a, R b, R c)
-{
-    if constexpr (std::is_same_v<R, float>) return __builtin_fmaf(a, b, c);
-    else return __builtin_fma(a, b, c);
-}
 
 // Every op reads the amplitudes from `in` and writes all of them to `out`;
 // the group loop alternates two arrays, so results never need copying back.
@@ -114,7 +119,9 @@ __device__ __forceinline__ void copy_amps(const Amps<C64, K> &in, Amps<C64, K> &
     for (int r = 0; r < (1 << K); ++r) out[r] = in[r];
 }
 
-template <bool C64, int K, int PJ, bool SWAP, bool CTRL>
+// REAL: the matrix has no imaginary parts (a Hadamard); the products with
+// its zero parts are left out, which changes no result.
+template <bool C64, int K, int PJ, bool SWAP, bool CTRL, bool REAL = false>
 __device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &out,
                                         const uint32_t (&li)[1 << K], COp &op)
 {
@@ -143,6 +150,11 @@ __device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &ou
         if constexpr (SWAP) {
             na = b;
             nb = a;
+        } else if constexpr (REAL) {
+            na.x = fmadd(m2, b.x, m0 * a.x);
+            na.y = fmadd(m2, b.y, m0 * a.y);
+            nb.x = fmadd(m6, b.x, m4 * a.x);
+            nb.y = fmadd(m6, b.y, m4 * a.y);
         } else {
             na.x = fmadd(-m3, b.y, fmadd(m2, b.x, fmadd(-m1, a.y, m0 * a.x)));
             na.y = fmadd(m3, b.x, fmadd(m2, b.y, fmadd(m1, a.x, m0 * a.y)));
@@ -335,21 +347,20 @@ __device__ __forceinline__ void apply_u4(const Amps<C64, K> &in, Amps<C64, K> &o
 #undef SV_U4_CASE
 }
 
-// Diagonal op (the quadratic phase form described with TileOp): the turn of
-// register combination r is base + sum_{k in r} coef_k + PR(r), so the phase
-// of every amplitude is a product of five evaluated phases and a constant.
-template <bool C64, int K>
-__device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op,
-                                           const uint64_t *dtab, int L, CGroup &G, uint64_t g,
-                                           uint32_t tid, const AmpT<C64> *tab)
+// The turns of a diagonal op (the quadratic phase form described with
+// TileOp) for this thread and tile: base, and coef_k for the register
+// positions k in LIN. Positions outside LIN are left zero, and so is base
+// unless BASE: callers pass only what the op's shape (TileOp.dlin) allows to
+// be non-zero.
+template <int K, uint32_t LIN, bool BASE>
+__device__ __forceinline__ void diag_turns(COp &op, const uint64_t *dtab, int L, CGroup &G,
+                                           uint64_t g, uint32_t tid, uint64_t &base,
+                                           uint64_t (&coef)[K])
 {
-    using A = AmpT<C64>;
-    constexpr int NR = 1 << K;
     const uint64_t *th = dtab + op.dthr + size_t(tid) * (K + 1);
-    uint64_t base = th[0];
-    uint64_t coef[K];
+    base = BASE ? th[0] : 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) coef[k] = th[1 + k];
+    for (int k = 0; k < K; ++k) coef[k] = ((LIN >> k) & 1u) ? th[1 + k] : 0;
     if (op.dout >= 0) {
         // Weights against the bits of g: uniform byte-table sums (scalar loads).
         CU64 *bt = (CU64 *)(dtab + op.dout);
@@ -359,14 +370,31 @@ __device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> 
                 w += bt[(size_t(b) * (L + 1) + l) * 256 + ((g >> (8 * b)) & 255u)];
             return w;
         };
-        base += ow(L);
-        for (int k = 0; k < L - K; ++k) {
-            const uint64_t w = ow(G.ns[k]);
-            base += ((tid >> k) & 1u) ? w : 0ull;
+        if constexpr (BASE) {
+            base += ow(L);
+            for (int k = 0; k < L - K; ++k) {
+                const uint64_t w = ow(G.ns[k]);
+                base += ((tid >> k) & 1u) ? w : 0ull;
+            }
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) coef[k] += ow(G.s[k]);
+        for (int k = 0; k < K; ++k)
+            if ((LIN >> k) & 1u) coef[k] += ow(G.s[k]);
     }
+}
+
+// Diagonal op: the turn of register combination r is base + sum_{k in r}
+// coef_k + PR(r), so the phase of every amplitude is a product of five
+// evaluated phases and a constant.
+template <bool C64, int K>
+__device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> &out, COp &op,
+                                           const uint64_t *dtab, int L, CGroup &G, uint64_t g,
+                                           uint32_t tid, const AmpT<C64> *tab)
+{
+    using A = AmpT<C64>;
+    constexpr int NR = 1 << K;
+    uint64_t base, coef[K];
+    diag_turns<K, (1u << K) - 1, true>(op, dtab, L, G, g, tid, base, coef);
     A e[NR];
     A ek[K];
     e[0] = turn_phase<C64>(base, tab);
@@ -388,6 +416,58 @@ __device__ __forceinline__ void apply_diag(const Amps<C64, K> &in, Amps<C64, K> 
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) out[r] = cmul(in[r], e[r]);
+}
+
+// The same op with its shape fixed at compile time: LIN and BASE as in
+// TileOp.dlin, and ONE the register combinations whose constant factor
+// e^{2 pi i PR(r) / 2^64} is exactly 1. Phases that are exactly 1 are neither
+// evaluated nor multiplied (a controlled phase on a register pivot changes
+// only the half of the amplitudes with the pivot set); the factors that
+// remain are multiplied in the generic op's order, so the results are the
+// same.
+template <bool C64, int K, uint32_t LIN, bool BASE, uint32_t ONE>
+__device__ __forceinline__ void apply_diag_shape(const Amps<C64, K> &in, Amps<C64, K> &out,
+                                                 COp &op, const uint64_t *dtab, int L, CGroup &G,
+                                                 uint64_t g, uint32_t tid, const AmpT<C64> *tab)
+{
+    using A = AmpT<C64>;
+    constexpr int NR = 1 << K;
+    uint64_t base, coef[K];
+    diag_turns<K, LIN, BASE>(op, dtab, L, G, g, tid, base, coef);
+    A ek[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if ((LIN >> k) & 1u) ek[k] = turn_phase<C64>(coef[k], tab);
+    // p[r]: the product of r's evaluated phases (set only where it is not 1).
+    A p[NR];
+    if constexpr (BASE) p[0] = turn_phase<C64>(base, tab);
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+        const uint32_t rl = uint32_t(r) & LIN;
+        if (rl == 0) {
+            if (BASE) p[r] = p[0];
+            continue;
+        }
+        const int k = 31 - __builtin_clz(rl);
+        const int prev = r ^ (1 << k);
+        p[r] = (!BASE && (uint32_t(prev) & LIN) == 0) ? ek[k] : cmul(p[prev], ek[k]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const bool one_p = !BASE && (uint32_t(r) & LIN) == 0;
+        const bool one_c = (ONE >> r) & 1u;
+        if (one_p && one_c) {
+            out[r] = in[r];
+            continue;
+        }
+        A c{};
+        if (!one_c) {
+            if constexpr (C64) { c.x = op.mf4[2 * r]; c.y = op.mf4[2 * r + 1]; }
+            else { c.x = op.m4[2 * r]; c.y = op.m4[2 * r + 1]; }
+        }
+        const A f = one_p ? c : (one_c ? p[r] : cmul(p[r], c));
+        out[r] = cmul(in[r], f);
+    }
 }
 
 // Applies one op of group G: in -> out.
@@ -468,6 +548,59 @@ __device__ __forceinline__ void st_amp(A *p, const A &v)
     else *p = v;
 }
 
+// Index bit of the s-th set bit of mask (mask uniform, s a constant).
+__device__ __forceinline__ uint64_t nth_bit(uint64_t mask, int s)
+{
+    for (int i = 0; i < s; ++i) mask &= mask - 1;
+    return mask & (~mask + 1);
+}
+
+// Direct transfers between HBM and a group's registers, with no LDS round
+// trip: a pass's first group can load its amplitudes from HBM and its last
+// group can store them there, when the threads' own bits keep the tile's low
+// index bits (coalesced accesses). rb[k] is the index bit of register bit k;
+// gb holds the tile's outside bits and the thread's own bits.
+template <bool C64, int K, bool NT>
+__device__ __forceinline__ void load_direct(const TileArgs &a, uint64_t gb, const uint64_t (&rb)[K],
+                                            uint32_t lbase, const uint32_t (&soff)[K],
+                                            uint32_t (&li)[1 << K], Amps<C64, K> &v)
+{
+    using A = AmpT<C64>;
+    const A *psi = static_cast<const A *>(a.psi);
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t l = lbase;
+        uint64_t x = gb;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) {
+                l |= soff[k];
+                x |= rb[k];
+            }
+        li[r] = l;
+        v[r] = ld_amp<NT>(&psi[x]);
+    }
+}
+
+// Register combination r goes to the index of combination xr[r] (the group's
+// exit map, or r itself); ob[k] is the index bit that register bit k is
+// written to (the pass's relabelled order when it has one).
+template <bool C64, int K, bool NT>
+__device__ __forceinline__ void store_direct(const TileArgs &a, uint64_t gb, const uint64_t (&ob)[K],
+                                             const uint32_t (&xr)[1 << K], const Amps<C64, K> &v)
+{
+    using A = AmpT<C64>;
+    A *psi = static_cast<A *>(a.psi);
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        uint64_t x = gb;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (xr[r] & (1u << k)) x |= ob[k];
+        st_amp<NT>(&psi[x], v[r]);
+    }
+}
+
 // Per-thread constants of one pass's walk over its tiles.
 template <int K>
 struct Walk {
@@ -509,8 +642,10 @@ __device__ __forceinline__ void walk_init(const TileArgs &a, AmpT<C64> *tab, Wal
 
 // Tile g (index bits outside the tile = gbase) from HBM into LDS, then a
 // barrier that orders LDS only (the previous tile's global stores may still
-// be in flight).
-template <bool C64, int K, bool NT>
+// be in flight). WAIT: the previous tile ended in direct stores, whose last
+// group read other threads' slots, so the slots are written only after a
+// barrier.
+template <bool C64, int K, bool NT, bool WAIT = false>
 __device__ __forceinline__ void tile_load(const TileArgs &a, const Walk<K> &w, uint64_t gbase,
                                           AmpT<C64> *lds)
 {
@@ -523,10 +658,13 @@ __device__ __forceinline__ void tile_load(const TileArgs &a, const Walk<K> &w, u
     uint64_t dtv = w.dt;
     uint32_t tv = w.tid;
     asm volatile("" : "+v"(dtv), "+v"(tv));
+    A pv[NR];
     if (w.active) {
-        A pv[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) pv[r] = ld_amp<NT>(&psi[gbase | dtv | w.roff[r]]);
+    }
+    if constexpr (WAIT) lds_barrier();
+    if (w.active) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tv + uint32_t(r) * w.W)] = pv[r];
     }
@@ -600,19 +738,24 @@ __device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v,
 // work-group: each tile is loaded, `groups(g, gbase, w)` runs the pass's
 // register groups on it (every group ending in a work-group barrier), and it
 // is stored. Threads tid >= 2^(L-K) (a tile smaller than the work-group) take
-// part in the barriers only.
-template <bool C64, int K, bool NT, typename Groups>
+// part in the barriers only. DF: the first group loads the tile from HBM
+// itself (load_direct); DL: the last group stores it (store_direct) and ends
+// without a barrier.
+template <bool C64, int K, bool NT, bool DF = false, bool DL = false, typename Groups>
 __device__ __forceinline__ void walk_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
                                            uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab,
                                            const Groups &groups)
 {
     Walk<K> w;
     walk_init<C64, K>(a, tab, w);
+    // A first group that loads from HBM runs its ops before any barrier:
+    // the phase table must be in LDS before.
+    if constexpr (DF) lds_barrier();
     for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
-        tile_load<C64, K, NT>(a, w, gbase, lds);
+        if constexpr (!DF) tile_load<C64, K, NT, DL>(a, w, gbase, lds);
         groups(g, gbase, w);
-        tile_store<C64, K, NT>(a, w, gbase, lds);
+        if constexpr (!DL) tile_store<C64, K, NT>(a, w, gbase, lds);
     }
 }
 
