@@ -89,12 +89,24 @@ bool direct_last(const TileArgs &a, const TileGroup &G, int K)
 const bool kJitDirect = env_int("SV_JIT_DIRECT", 1) != 0;
 
 
+// Register combination that combination r of group G is written back as: its
+// exit map (TileGroup), or r itself.
+uint32_t exit_of(const TileGroup &G, int K, int r)
+{
+    if (!G.has_exit) return uint32_t(r);
+    uint32_t x = G.xb;
+    for (int k = 0; k < K; ++k)
+        if (r & (1 << k)) x ^= G.xs[k];
+    return x;
+}
+
+
 std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp *ops, int K,
                         bool c64, bool nt)
 {
     const int L = a.L;
     const uint32_t size = 1u << L;
-    const uint32_t slots = c64 ? size + (size >> 5) : size + (size >> 4);
+    const uint32_t slots = tile_slots(c64, size);
     const int threads = 1 << (L - K);
     const int NR = 1 << K;
     const int ng = a.ngroups;
@@ -140,22 +152,14 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
         o << ", a.tmask);\n    const uint64_t obl[K] = {";
         for (int k = 0; k < K; ++k) o << (k ? ", " : "") << "nth_bit(a.tmask, " << out_bit(a, G.s[k]) << ")";
         o << "};\n    const uint32_t xrl[1 << K] = {";
-        for (int r = 0; r < NR; ++r) {
-            uint32_t x = uint32_t(r);
-            if (G.has_exit) {
-                x = G.xb;
-                for (int k = 0; k < K; ++k)
-                    if (r & (1 << k)) x ^= G.xs[k];
-            }
-            o << (r ? ", " : "") << x << "u";
-        }
+        for (int r = 0; r < NR; ++r) o << (r ? ", " : "") << exit_of(G, K, r) << "u";
         o << "};\n";
     }
     // tid is made opaque at every group, so that nothing derived from it (slot
     // addresses, per-thread diagonal rows) is hoisted out of the tile loop
     // and held in registers through all the tiles. Every thread of the
     // work-group holds amplitudes (2^(L-K) threads).
-    o << "    auto prog = [&](uint64_t g, uint64_t gbase, const Walk<K> &w) {\n";
+    o << "    auto prog = [&](uint64_t g, uint64_t gbase, const Walk<K> &w, const A (&cur)[1 << K]) {\n";
     for (int gi = 0; gi < ng; ++gi) {
         const TileGroup &G = groups[gi];
         const bool first = gi == 0 && df, last = gi == ng - 1 && dl;
@@ -172,8 +176,7 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
           << "            uint32_t li[1 << K];\n"
           << "            A v[1 << K], u[1 << K];\n";
         if (first)
-            o << "            load_direct<C64, K, " << (nt ? "true" : "false")
-              << ">(a, gbase | dfirst, rbf, lbase, soff, li, v);\n";
+            o << "            take_regs<C64, K>(cur, lbase, soff, li, v);\n";
         else
             o << "            gather<C64, K>(lds, lbase, soff, li, v);\n";
         const char *arr[2] = {"v", "u"};
@@ -222,6 +225,10 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
                     cond = (cond.empty() ? "" : cond + " && ") + "((gbase & " + m + ") == " + m + ")";
                 }
             }
+            // Ops are scheduled one after the other: hoisting an op's matrix
+            // loads over the op before it holds two matrices in scalar
+            // registers (64 each for a 4x4) and spills them to vector lanes.
+            if (oi > 0) o << "            __builtin_amdgcn_sched_barrier(0);\n";
             if (cond.empty())
                 o << "            " << core.str() << "\n";
             else
@@ -249,16 +256,34 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
         // A first group that loaded from HBM writes slots that other threads
         // of the previous tile may still be reading.
         if (first) o << "            lds_barrier();\n";
-        o << "            scatter<C64, K>(lds, " << fin << ", li, lbase, soff, G, "
-          << (G.has_exit ? "true" : "false") << ");\n"
-          << "            __builtin_amdgcn_s_setprio(0);\n"
+        if (G.has_exit) {
+            // the exit map as constants: every slot offset is an immediate
+            o << "            const uint32_t xr[1 << K] = {";
+            for (int r = 0; r < NR; ++r) o << (r ? ", " : "") << exit_of(G, K, r) << "u";
+            o << "};\n            write_map<C64, K>(lds, " << fin << ", lbase, soff, xr);\n";
+        } else {
+            o << "            scatter<C64, K>(lds, " << fin << ", li, lbase, soff, G, false);\n";
+        }
+        o << "            __builtin_amdgcn_s_setprio(0);\n"
           << "            lds_barrier();\n"
           << "        }\n";
     }
-    o << "    };\n"
+    o << "    };\n";
+    // The tile's fetch: in the first group's layout (direct) or the
+    // tile-load layout.
+    if (df)
+        o << "    auto fetch = [&](uint64_t gb, const Walk<K> &, A (&p)[1 << K]) {\n"
+          << "        fetch_direct<C64, K, " << (nt ? "true" : "false") << ">(a, gb | dfirst, rbf, p);\n"
+          << "    };\n";
+    else
+        o << "    TileFetch<C64, K, " << (nt ? "true" : "false") << "> fetch{a};\n";
+    // Each work-group walks a contiguous range of tiles: the stores of one
+    // tile and the loads of the next fall on neighbouring lines.
+    o << "    const uint64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;\n"
+      << "    const uint64_t t0b = uint64_t(blockIdx.x) * per;\n"
+      << "    const uint64_t t1b = t0b + per < a.ntiles ? t0b + per : a.ntiles;\n"
       << "    walk_tiles<C64, K, " << (nt ? "true" : "false") << ", " << (df ? "true" : "false")
-      << ", " << (dl ? "true" : "false")
-      << ">(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab, prog);\n}\n";
+      << ", " << (dl ? "true" : "false") << ">(a, t0b, t1b, 1, lds, tab, prog, fetch);\n}\n";
     if (std::getenv("SV_JIT_VERBOSE"))
         std::fprintf(stderr, "[sv jit] pass: %d groups, direct first %d, direct last %d, permute %d\n",
                      ng, int(df), int(dl), int(a.permute));

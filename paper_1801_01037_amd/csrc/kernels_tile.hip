@@ -26,7 +26,7 @@ namespace svk {
 size_t tile_lds_bytes(bool c64, int L, bool diag)
 {
     const size_t size = size_t(1) << L;
-    const size_t slots = c64 ? size + (size >> 5) : size + (size >> 4);
+    const size_t slots = tile_slots(c64, uint32_t(size));
     const size_t eb = c64 ? 8 : 16;
     return (slots + (diag ? 512 : 0)) * eb;
 }
@@ -43,7 +43,8 @@ struct RecordedGroups {
     AmpT<C64> *lds;
     const AmpT<C64> *tab;
 
-    __device__ __forceinline__ void operator()(uint64_t g, uint64_t gbase, const Walk<K> &w) const
+    __device__ __forceinline__ void operator()(uint64_t g, uint64_t gbase, const Walk<K> &w,
+                                               const Amps<C64, K> &) const
     {
         using A = AmpT<C64>;
         constexpr int NR = 1 << K;
@@ -92,7 +93,8 @@ template <bool C64, int K, bool NT = false>
 __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
                                           uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab)
 {
-    walk_tiles<C64, K, NT>(a, g0, gend, gstep, lds, tab, RecordedGroups<C64, K>{a, lds, tab});
+    walk_tiles<C64, K, NT>(a, g0, gend, gstep, lds, tab, RecordedGroups<C64, K>{a, lds, tab},
+                           TileFetch<C64, K, NT>{a});
 }
 
 template <bool C64>
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(MAXT) void k_tile(TileArgs a)
     using A = AmpT<C64>;
     A *lds = lds_base<C64>();
     const uint32_t size = 1u << a.L;
-    A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+    A *tab = lds + tile_slots(C64, size);
     run_tiles<C64, K, NT>(a, blockIdx.x, a.ntiles, gridDim.x, lds, tab);
 }
 
@@ -138,7 +140,7 @@ void k_level(BatchArgs b)
         a.ngroups = pc.ngroups; a.has_diag = pc.has_diag; a.permute = pc.permute; a.osrc = pc.osrc;
         if (threadIdx.x == 0) b.t_start[ti] = wall_clock64();
         const uint32_t size = 1u << a.L;
-        A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+        A *tab = lds + tile_slots(C64, size);
         run_tiles<C64, K>(a, tile0, uint64_t(tile0) + ntiles, 1, lds, tab);
         if (threadIdx.x == 0) b.t_end[ti] = wall_clock64();
         lds_barrier();   // the next task reuses LDS
@@ -172,7 +174,7 @@ void k_persist(PersistArgs p)
             a.L = pc.L; a.nlow = pc.nlow; a.nnon = pc.nnon; a.group0 = pc.group0;
             a.ngroups = pc.ngroups; a.has_diag = pc.has_diag; a.permute = pc.permute; a.osrc = pc.osrc;
             const uint32_t size = 1u << a.L;
-            A *tab = lds + (C64 ? size + (size >> 5) : size + (size >> 4));
+            A *tab = lds + tile_slots(C64, size);
             run_tiles<C64, K>(a, 0, a.ntiles, 1, lds, tab);
             // The next pass loads what this one stored, from other waves of
             // the work-group: release the stores, meet, acquire.

@@ -386,12 +386,14 @@ std::vector<int> cycle_order(const Layout &lay, int nlow)
 struct TileGeom {
     int L, K, nlow;
     bool fuse4;     // merge register-local runs into 4x4 ops
+    bool c64;
 };
 
 TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
 {
     const bool c64 = dt == SV_C64;
     TileGeom g;
+    g.c64 = c64;
     int L = c64 ? kTileL64 : kTileL128;
     int K = c64 ? kTileK64 : kTileK128;
     // Fixed low tile qubits: contiguous runs of one 128 B line, so no line is
@@ -900,6 +902,31 @@ bool diag_tables(const POp &op, const std::vector<int> &T, const std::vector<int
     return true;
 }
 
+// Thread bits of a register group: thread bit k is local tile bit ns[k],
+// over the tile bits not in S. Complex128: 16-byte LDS accesses are free of
+// bank conflicts when the slots of 16 neighbouring lanes differ modulo 16
+// (reads) and of 8 modulo 8 (writes); in the slot map l + l/16 + l/256,
+// local bit b adds 2^(b mod 4) modulo 16, so thread bits 0..3 take a free bit
+// of class b mod 4 = 0, 1, 2, 3 (the lowest: the tile's low bits stay on the
+// low thread bits, which keeps direct transfers coalesced), and the rest
+// follow in ascending order. Complex64: ascending.
+void thread_order(const std::vector<int> &S, const TileGeom &geo, int32_t *ns)
+{
+    std::vector<int> fr, order;
+    for (int b = 0; b < geo.L; ++b)
+        if (std::find(S.begin(), S.end(), b) == S.end()) fr.push_back(b);
+    if (!geo.c64)
+        for (int k = 0; k < 4 && int(order.size()) < int(fr.size()); ++k)
+            for (int b : fr)
+                if (b % 4 == k) {
+                    order.push_back(b);
+                    break;
+                }
+    for (int b : fr)
+        if (std::find(order.begin(), order.end(), b) == order.end()) order.push_back(b);
+    for (size_t k = 0; k < order.size(); ++k) ns[k] = order[k];
+}
+
 struct Flat {
     bool ok = true;                 // false: a diagonal pair term on two outside bits
     std::vector<TileGroup> groups;
@@ -937,9 +964,7 @@ Flat flatten(int n, const TileGeom &geo, const std::vector<PPass> &passes)
         for (const PGroup &g : pass.groups) {
             TileGroup tg{};
             for (int k = 0; k < geo.K; ++k) tg.s[k] = g.S[k];
-            int nn = 0;
-            for (int b = 0; b < geo.L; ++b)
-                if (std::find(g.S.begin(), g.S.end(), b) == g.S.end()) tg.ns[nn++] = b;
+            thread_order(g.S, geo, tg.ns);
             tg.op0 = int(f.ops.size());
             tg.nops = int(g.ops.size());
             tg.has_exit = g.folded.empty() ? 0 : 1;

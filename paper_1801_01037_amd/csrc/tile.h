@@ -35,6 +35,14 @@ constexpr int kTileL64 = 12, kTileK64 = 4;     // 32 KiB of complex64 per tile, 
 constexpr int kTileThreads = 512;              // upper bound of 2^(L-K)
 
 enum TileOpKind : int32_t { TOP_U = 0, TOP_SWAP = 1, TOP_DIAG = 2, TOP_U4 = 3 };
+
+// LDS slots that hold a tile of `size` amplitudes: local index l sits in slot
+// l + l/32 (complex64) or l + l/16 + l/256 (complex128); the padding keeps
+// the accesses of a register group free of bank conflicts.
+constexpr uint32_t tile_slots(bool c64, uint32_t size)
+{
+    return c64 ? size + (size >> 5) : size + (size >> 4) + (size >> 8);
+}
 constexpr uint32_t kDiagBase = 1u << 31;   // TileOp.dlin: base can be non-zero
 
 // A diagonal op multiplies each amplitude by e^{2 pi i T / 2^64}, where T is
@@ -89,7 +97,7 @@ struct TileOp {
 
 struct TileGroup {
     int32_t s[kTileMaxK];          // local tile bits held in registers, ascending
-    int32_t ns[kTileMaxL];         // the other L-K local bits, ascending
+    int32_t ns[kTileMaxL];         // the other L-K local bits: thread bit k is local bit ns[k]
     int32_t op0, nops;
     // Exchanges (X, CNOT) on register bits that end the group are not ops:
     // the write-back sends register combination r to position

@@ -41,10 +41,21 @@ using RealT = std::conditional_t<C64, float, double>;
 template <bool C64>
 using AmpT = std::conditional_t<C64, fv2, dv2>;
 
+// LDS slot of local index l: one padding slot per 32 amplitudes
+// (complex64), or one per 16 and one more per 256 (complex128). A 16-byte
+// read is served 16 lanes at a time and a write 8 at a time, free of bank
+// conflicts when those lanes' slots differ modulo 16 and 8; in the
+// complex128 map, local bit b adds 2^(b mod 4) to the slot modulo 16, so
+// each register group gives its low thread bits one free tile bit of each
+// class b mod 4 (the planner's thread order, TileGroup.ns). The map adds
+// over indices with no common bit, lds_slot(a | b) = lds_slot(a) +
+// lds_slot(b), since no carry from the low bits can reach a shifted part: a
+// thread's slots are its base slot plus offsets that depend on the register
+// combination only (constants in a compiled pass).
 template <bool C64>
 __device__ __forceinline__ uint32_t lds_slot(uint32_t l)
 {
-    return C64 ? l + (l >> 5) : l + (l >> 4);
+    return C64 ? l + (l >> 5) : l + (l >> 4) + (l >> 8);
 }
 
 // Scatters the low bits of x, in order, onto the set bits of mask (the
@@ -503,23 +514,32 @@ __device__ __forceinline__ void write_exit(AmpT<C64> *lds, const Amps<C64, K> &v
                                            const uint32_t (&soff)[K], CGroup &G)
 {
     constexpr int NR = 1 << K;
-    uint32_t mb = lbase, ms[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        mb |= ((G.xb >> k) & 1u) ? soff[k] : 0u;
-        uint32_t m = 0;
-        const uint32_t col = G.xs[k];
-#pragma unroll
-        for (int k2 = 0; k2 < K; ++k2) m |= ((col >> k2) & 1u) ? soff[k2] : 0u;
-        ms[k] = m;
-    }
+    const uint32_t sb = lds_slot<C64>(lbase);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        uint32_t l = mb;
+        uint32_t x = G.xb;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (r & (1 << k)) l ^= ms[k];
-        lds[lds_slot<C64>(l)] = val[r];
+            if (r & (1 << k)) x ^= G.xs[k];
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) c |= ((x >> k) & 1u) ? soff[k] : 0u;
+        lds[sb + lds_slot<C64>(c)] = val[r];
+    }
+}
+
+// The same with the map given as a table (a compiled pass: constants).
+template <bool C64, int K>
+__device__ __forceinline__ void write_map(AmpT<C64> *lds, const Amps<C64, K> &val, uint32_t lbase,
+                                          const uint32_t (&soff)[K], const uint32_t (&xr)[1 << K])
+{
+    const uint32_t sb = lds_slot<C64>(lbase);
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) c |= ((xr[r] >> k) & 1u) ? soff[k] : 0u;
+        lds[sb + lds_slot<C64>(c)] = val[r];
     }
 }
 
@@ -556,29 +576,42 @@ __device__ __forceinline__ uint64_t nth_bit(uint64_t mask, int s)
 }
 
 // Direct transfers between HBM and a group's registers, with no LDS round
-// trip: a pass's first group can load its amplitudes from HBM and its last
-// group can store them there, when the threads' own bits keep the tile's low
-// index bits (coalesced accesses). rb[k] is the index bit of register bit k;
-// gb holds the tile's outside bits and the thread's own bits.
+// trip: a pass's first group can take its amplitudes fetched from HBM in its
+// own layout and its last group can store them there, when the threads' own
+// bits keep the tile's low index bits (coalesced accesses). rb[k] is the
+// index bit of register bit k; gb holds the tile's outside bits and the
+// thread's own bits.
 template <bool C64, int K, bool NT>
-__device__ __forceinline__ void load_direct(const TileArgs &a, uint64_t gb, const uint64_t (&rb)[K],
-                                            uint32_t lbase, const uint32_t (&soff)[K],
-                                            uint32_t (&li)[1 << K], Amps<C64, K> &v)
+__device__ __forceinline__ void fetch_direct(const TileArgs &a, uint64_t gb, const uint64_t (&rb)[K],
+                                             Amps<C64, K> &v)
 {
     using A = AmpT<C64>;
     const A *psi = static_cast<const A *>(a.psi);
 #pragma unroll
     for (int r = 0; r < (1 << K); ++r) {
-        uint32_t l = lbase;
         uint64_t x = gb;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (r & (1 << k)) {
-                l |= soff[k];
-                x |= rb[k];
-            }
-        li[r] = l;
+            if (r & (1 << k)) x |= rb[k];
         v[r] = ld_amp<NT>(&psi[x]);
+    }
+}
+
+// A group's registers taken from amplitudes fetched in its own layout, with
+// their local indices (as gather gives them).
+template <bool C64, int K>
+__device__ __forceinline__ void take_regs(const Amps<C64, K> &cur, uint32_t lbase,
+                                          const uint32_t (&soff)[K], uint32_t (&li)[1 << K],
+                                          Amps<C64, K> &v)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) c |= soff[k];
+        li[r] = lbase | c;
+        v[r] = cur[r];
     }
 }
 
@@ -601,23 +634,48 @@ __device__ __forceinline__ void store_direct(const TileArgs &a, uint64_t gb, con
     }
 }
 
-// Per-thread constants of one pass's walk over its tiles.
+// Per-thread constants of one pass's walk over its tiles. Register r's
+// offsets are linear in the bits of r, so only the K basis values are kept;
+// each use rebuilds r's offset from them (scalar ORs) instead of holding all
+// 2^K offsets in scalar registers through the tile loop.
 template <int K>
 struct Walk {
     uint32_t W;            // threads holding amplitudes: 2^(L-K)
     uint32_t tid;
     bool active;           // tid < W (a tile smaller than the work-group)
     uint64_t dt;           // this thread's tile bits as index bits
-    uint64_t roff[1 << K]; // register r's index bits
-    uint32_t proff[1 << K];// register r's local index under the relabelled store
+    uint64_t rbit[K];      // index bit of register bit k
+    uint32_t pbit[K];      // local bit that register bit k reads under the relabelled store
 };
+
+// Offset of register combination r from per-bit basis values b (each a
+// single bit): their OR over the set bits of r. The basis is copied through
+// an opaque move first, so the 2^K combinations are formed where they are
+// used rather than hoisted out of the tile loop.
+template <int K, typename T>
+__device__ __forceinline__ void reg_offsets(const T (&b)[K], T (&out)[1 << K])
+{
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = b[k];
+        asm volatile("" : "+s"(v[k]));
+    }
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        T x = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) x |= v[k];
+        out[r] = x;
+    }
+}
 
 // Loads the phase table (passes with diagonal ops) and the walk constants.
 template <bool C64, int K>
 __device__ __forceinline__ void walk_init(const TileArgs &a, AmpT<C64> *tab, Walk<K> &w)
 {
     using A = AmpT<C64>;
-    constexpr int NR = 1 << K;
     w.W = 1u << (a.L - K);
     w.tid = threadIdx.x;
     w.active = w.tid < w.W;
@@ -627,27 +685,20 @@ __device__ __forceinline__ void walk_init(const TileArgs &a, AmpT<C64> *tab, Wal
     }
     w.dt = deposit(w.tid, a.tmask);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) w.roff[r] = deposit(uint64_t(r) * w.W, a.tmask);
+    for (int k = 0; k < K; ++k) w.rbit[k] = nth_bit(a.tmask, a.L - K + k);
     // Relabelled store: output local index lo reads input local index
     // perm(lo), bit j of lo moving to bit osrc_j; perm(tid + r W) =
     // perm(tid) | perm(r W).
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        uint32_t x = 0;
-        for (int k = 0; k < K; ++k)
-            x |= uint32_t((r >> k) & 1) << uint32_t((a.osrc >> (4 * (a.L - K + k))) & 15u);
-        w.proff[r] = x;
-    }
+    for (int k = 0; k < K; ++k) w.pbit[k] = 1u << uint32_t((a.osrc >> (4 * (a.L - K + k))) & 15u);
 }
 
-// Tile g (index bits outside the tile = gbase) from HBM into LDS, then a
-// barrier that orders LDS only (the previous tile's global stores may still
-// be in flight). WAIT: the previous tile ended in direct stores, whose last
-// group read other threads' slots, so the slots are written only after a
-// barrier.
-template <bool C64, int K, bool NT, bool WAIT = false>
-__device__ __forceinline__ void tile_load(const TileArgs &a, const Walk<K> &w, uint64_t gbase,
-                                          AmpT<C64> *lds)
+// Tile g's amplitudes (index bits outside the tile = gbase) from HBM into
+// registers, in the tile-load layout: thread tid holds local indices
+// tid + r W.
+template <bool C64, int K, bool NT>
+__device__ __forceinline__ void tile_fetch(const TileArgs &a, const Walk<K> &w, uint64_t gbase,
+                                           Amps<C64, K> &pv)
 {
     using A = AmpT<C64>;
     constexpr int NR = 1 << K;
@@ -656,20 +707,42 @@ __device__ __forceinline__ void tile_load(const TileArgs &a, const Walk<K> &w, u
     // recomputed at each use instead of being hoisted out of the tile loop
     // and held in registers through all the groups.
     uint64_t dtv = w.dt;
-    uint32_t tv = w.tid;
-    asm volatile("" : "+v"(dtv), "+v"(tv));
-    A pv[NR];
+    asm volatile("" : "+v"(dtv));
     if (w.active) {
+        uint64_t roff[NR];
+        reg_offsets<K>(w.rbit, roff);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) pv[r] = ld_amp<NT>(&psi[gbase | dtv | w.roff[r]]);
+        for (int r = 0; r < NR; ++r) pv[r] = ld_amp<NT>(&psi[gbase | dtv | roff[r]]);
     }
+}
+
+// Fetched registers into LDS, then a barrier that orders LDS only (the
+// previous tile's global stores may still be in flight). WAIT: the previous
+// tile ended in direct stores, whose last group read other threads' slots,
+// so the slots are written only after a barrier.
+template <bool C64, int K, bool WAIT = false>
+__device__ __forceinline__ void tile_fill(const Walk<K> &w, const Amps<C64, K> &pv, AmpT<C64> *lds)
+{
+    constexpr int NR = 1 << K;
+    uint32_t tv = w.tid;
+    asm volatile("" : "+v"(tv));
     if constexpr (WAIT) lds_barrier();
     if (w.active) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tv + uint32_t(r) * w.W)] = pv[r];
+        for (int r = 0; r < NR; ++r) lds[lds_slot<C64>(tv) + lds_slot<C64>(uint32_t(r) * w.W)] = pv[r];
     }
     lds_barrier();
 }
+
+// The tile-load layout's fetch, as a callable for walk_tiles.
+template <bool C64, int K, bool NT>
+struct TileFetch {
+    const TileArgs &a;
+    __device__ __forceinline__ void operator()(uint64_t gbase, const Walk<K> &w, Amps<C64, K> &pv) const
+    {
+        tile_fetch<C64, K, NT>(a, w, gbase, pv);
+    }
+};
 
 // The tile from LDS back to HBM, in the relabelled order when the pass has
 // one. Each thread stores the slots it filled, so the next fill needs no
@@ -687,15 +760,21 @@ __device__ __forceinline__ void tile_store(const TileArgs &a, const Walk<K> &w, 
         uint32_t ts = w.tid;
         asm volatile("" : "+v"(dts), "+v"(ts));
         const uint64_t gb = gbase | dts;
+        uint64_t roff[NR];
+        reg_offsets<K>(w.rbit, roff);
         if (permute) {
             uint32_t pt = 0;
             for (int j = 0; j < a.L - K; ++j)
                 pt |= ((ts >> j) & 1u) << uint32_t((a.osrc >> (4 * j)) & 15u);
+            uint32_t proff[NR];
+            reg_offsets<K>(w.pbit, proff);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) st_amp<NT>(&psi[gb | w.roff[r]], lds[lds_slot<C64>(pt | w.proff[r])]);
+            for (int r = 0; r < NR; ++r)
+                st_amp<NT>(&psi[gb | roff[r]], lds[lds_slot<C64>(pt) + lds_slot<C64>(proff[r])]);
         } else {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) st_amp<NT>(&psi[gb | w.roff[r]], lds[lds_slot<C64>(ts + uint32_t(r) * w.W)]);
+            for (int r = 0; r < NR; ++r)
+                st_amp<NT>(&psi[gb | roff[r]], lds[lds_slot<C64>(ts) + lds_slot<C64>(uint32_t(r) * w.W)]);
         }
     }
     if (permute) lds_barrier();
@@ -709,14 +788,15 @@ __device__ __forceinline__ void gather(const AmpT<C64> *lds, uint32_t lbase,
                                        const uint32_t (&soff)[K], uint32_t (&li)[1 << K],
                                        Amps<C64, K> &v)
 {
+    const uint32_t sb = lds_slot<C64>(lbase);
 #pragma unroll
     for (int r = 0; r < (1 << K); ++r) {
-        uint32_t l = lbase;
+        uint32_t c = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (r & (1 << k)) l |= soff[k];
-        li[r] = l;
-        v[r] = lds[lds_slot<C64>(l)];
+            if (r & (1 << k)) c |= soff[k];
+        li[r] = lbase | c;
+        v[r] = lds[sb + lds_slot<C64>(c)];
     }
 }
 
@@ -726,35 +806,47 @@ __device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v,
                                         const uint32_t (&li)[1 << K], uint32_t lbase,
                                         const uint32_t (&soff)[K], CGroup &G, bool exit_map)
 {
+    (void)li;
     if (exit_map) {
         write_exit<C64, K>(lds, v, lbase, soff, G);
     } else {
+        const uint32_t sb = lds_slot<C64>(lbase);
 #pragma unroll
-        for (int r = 0; r < (1 << K); ++r) lds[lds_slot<C64>(li[r])] = v[r];
+        for (int r = 0; r < (1 << K); ++r) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (r & (1 << k)) c |= soff[k];
+            lds[sb + lds_slot<C64>(c)] = v[r];
+        }
     }
 }
 
 // Processes tiles g = g0, g0 + gstep, ... below gend of the pass `a` with one
-// work-group: each tile is loaded, `groups(g, gbase, w)` runs the pass's
-// register groups on it (every group ending in a work-group barrier), and it
-// is stored. Threads tid >= 2^(L-K) (a tile smaller than the work-group) take
-// part in the barriers only. DF: the first group loads the tile from HBM
-// itself (load_direct); DL: the last group stores it (store_direct) and ends
-// without a barrier.
-template <bool C64, int K, bool NT, bool DF = false, bool DL = false, typename Groups>
+// work-group: each tile is fetched into registers (`fetch`: the tile-load
+// layout, or with DF the first group's own layout), put in LDS (unless DF),
+// `groups(g, gbase, w, regs)` runs the pass's register groups on it (every
+// group ending in a work-group barrier; with DF the first group takes the
+// fetched registers), and it is stored (unless DL: the last group stores it
+// and ends without a barrier). Threads tid >= 2^(L-K) (a tile smaller than
+// the work-group) take part in the barriers only.
+template <bool C64, int K, bool NT, bool DF = false, bool DL = false, typename Groups,
+          typename Fetch>
 __device__ __forceinline__ void walk_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
                                            uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab,
-                                           const Groups &groups)
+                                           const Groups &groups, const Fetch &fetch)
 {
     Walk<K> w;
     walk_init<C64, K>(a, tab, w);
-    // A first group that loads from HBM runs its ops before any barrier:
-    // the phase table must be in LDS before.
+    // A first group that takes fetched registers runs its ops before any
+    // barrier: the phase table must be in LDS before.
     if constexpr (DF) lds_barrier();
     for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
-        if constexpr (!DF) tile_load<C64, K, NT, DL>(a, w, gbase, lds);
-        groups(g, gbase, w);
+        Amps<C64, K> cur;
+        fetch(gbase, w, cur);
+        if constexpr (!DF) tile_fill<C64, K, DL>(w, cur, lds);
+        groups(g, gbase, w, cur);
         if constexpr (!DL) tile_store<C64, K, NT>(a, w, gbase, lds);
     }
 }
