@@ -173,12 +173,11 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
         o << ";\n            const uint32_t soff[K] = {";
         for (int k = 0; k < K; ++k) o << (k ? ", " : "") << (1u << G.s[k]) << "u";
         o << "};\n"
-          << "            uint32_t li[1 << K];\n"
           << "            A v[1 << K], u[1 << K];\n";
         if (first)
-            o << "            take_regs<C64, K>(cur, lbase, soff, li, v);\n";
+            o << "            take_regs<C64, K>(cur, v);\n";
         else
-            o << "            gather<C64, K>(lds, lbase, soff, li, v);\n";
+            o << "            gather<C64, K>(lds, lbase, soff, v);\n";
         const char *arr[2] = {"v", "u"};
         for (int oi = 0; oi < G.nops; ++oi) {
             const TileOp &t = ops[G.op0 + oi];
@@ -213,7 +212,7 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
                                       t.m[5] == 0.0 && t.m[7] == 0.0;
                     core << "pair_pj<C64, K, " << t.pj << ", " << sw << ", "
                          << ((t.lctrl >= 0 || t.lcm) ? "true" : "false") << ", "
-                         << (real ? "true" : "false") << ">(" << in << ", " << out << ", li, ops["
+                         << (real ? "true" : "false") << ">(" << in << ", " << out << ", lbase, soff, ops["
                          << k << "]);";
                 }
             }
@@ -262,21 +261,20 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
             for (int r = 0; r < NR; ++r) o << (r ? ", " : "") << exit_of(G, K, r) << "u";
             o << "};\n            write_map<C64, K>(lds, " << fin << ", lbase, soff, xr);\n";
         } else {
-            o << "            scatter<C64, K>(lds, " << fin << ", li, lbase, soff, G, false);\n";
+            o << "            scatter<C64, K>(lds, " << fin << ", lbase, soff, G, false);\n";
         }
         o << "            __builtin_amdgcn_s_setprio(0);\n"
           << "            lds_barrier();\n"
           << "        }\n";
     }
     o << "    };\n";
-    // The tile's fetch: in the first group's layout (direct) or the
-    // tile-load layout.
+    // A direct first group's fetch: in its own layout.
     if (df)
         o << "    auto fetch = [&](uint64_t gb, const Walk<K> &, A (&p)[1 << K]) {\n"
           << "        fetch_direct<C64, K, " << (nt ? "true" : "false") << ">(a, gb | dfirst, rbf, p);\n"
           << "    };\n";
     else
-        o << "    TileFetch<C64, K, " << (nt ? "true" : "false") << "> fetch{a};\n";
+        o << "    NoFetch fetch;\n";
     // Each work-group walks a contiguous range of tiles: the stores of one
     // tile and the loads of the next fall on neighbouring lines.
     o << "    const uint64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;\n"

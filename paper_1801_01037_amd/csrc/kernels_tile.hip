@@ -62,9 +62,8 @@ struct RecordedGroups {
                 uint32_t soff[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) soff[k] = 1u << G.s[k];
-                uint32_t li[NR];
                 A v[NR], u[NR];
-                gather<C64, K>(lds, lbase, soff, li, v);
+                gather<C64, K>(lds, lbase, soff, v);
                 // Ops alternate v -> u and u -> v; the group ends in either.
                 // The write-back applies the group's exit exchanges: only this
                 // thread's own slots are permuted, so no barrier is needed.
@@ -72,15 +71,15 @@ struct RecordedGroups {
                 const bool exit_map = G.has_exit != 0;
                 for (int oi = 0;; oi += 2) {
                     if (oi == nops) {
-                        scatter<C64, K>(lds, v, li, lbase, soff, G, exit_map);
+                        scatter<C64, K>(lds, v, lbase, soff, G, exit_map);
                         break;
                     }
-                    apply_op<C64, K>(v, u, li, ops[G.op0 + oi], a.dtab, a.L, G, g, gbase, w.tid, tab);
+                    apply_op<C64, K>(v, u, lbase, soff, ops[G.op0 + oi], a.dtab, a.L, G, g, gbase, w.tid, tab);
                     if (oi + 1 == nops) {
-                        scatter<C64, K>(lds, u, li, lbase, soff, G, exit_map);
+                        scatter<C64, K>(lds, u, lbase, soff, G, exit_map);
                         break;
                     }
-                    apply_op<C64, K>(u, v, li, ops[G.op0 + oi + 1], a.dtab, a.L, G, g, gbase, w.tid, tab);
+                    apply_op<C64, K>(u, v, lbase, soff, ops[G.op0 + oi + 1], a.dtab, a.L, G, g, gbase, w.tid, tab);
                 }
             }
             __builtin_amdgcn_s_setprio(0);
@@ -94,7 +93,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs &a, uint64_t g0, uint64
                                           uint64_t gstep, AmpT<C64> *lds, AmpT<C64> *tab)
 {
     walk_tiles<C64, K, NT>(a, g0, gend, gstep, lds, tab, RecordedGroups<C64, K>{a, lds, tab},
-                           TileFetch<C64, K, NT>{a});
+                           NoFetch{});
 }
 
 template <bool C64>

@@ -133,14 +133,15 @@ __device__ __forceinline__ void copy_amps(const Amps<C64, K> &in, Amps<C64, K> &
 // REAL: the matrix has no imaginary parts (a Hadamard); the products with
 // its zero parts are left out, which changes no result.
 template <bool C64, int K, int PJ, bool SWAP, bool CTRL, bool REAL = false>
-__device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &out,
-                                        const uint32_t (&li)[1 << K], COp &op)
+__device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &out, uint32_t lbase,
+                                        const uint32_t (&soff)[K], COp &op)
 {
     using R = RealT<C64>;
     using A = AmpT<C64>;
     constexpr int NR = 1 << K;
     // The tile-bit controls: one (lctrl), or several (lcm).
     const uint32_t lm = op.lcm ? op.lcm : (op.lctrl >= 0 ? 1u << op.lctrl : 0u);
+    const uint32_t lb = lbase & lm;
     R m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0, m5 = 0, m6 = 0, m7 = 0;
     if constexpr (!SWAP) {
         if constexpr (C64) {
@@ -173,7 +174,13 @@ __device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &ou
             nb.y = fmadd(m7, b.x, fmadd(m6, b.y, fmadd(m5, a.x, m4 * a.y)));
         }
         if constexpr (CTRL) {
-            const bool on = (li[r] & lm) == lm;
+            // the controls of local index lbase | c(r): lbase and c(r)
+            // share no bit, so the thread's part is tested once
+            uint32_t c = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (r & (1 << k)) c |= soff[k];
+            const bool on = (lb | (c & lm)) == lm;
             out[r] = on ? na : a;
             out[r1] = on ? nb : b;
         } else {
@@ -184,24 +191,24 @@ __device__ __forceinline__ void pair_pj(const Amps<C64, K> &in, Amps<C64, K> &ou
 }
 
 template <bool C64, int K, bool SWAP, bool CTRL>
-__device__ __forceinline__ void apply_pair(const Amps<C64, K> &in, Amps<C64, K> &out,
-                                           const uint32_t (&li)[1 << K], COp &op)
+__device__ __forceinline__ void apply_pair(const Amps<C64, K> &in, Amps<C64, K> &out, uint32_t lbase,
+                                           const uint32_t (&soff)[K], COp &op)
 {
     // The planner emits positions below K only; the other arms are unreachable
     // (an arm that wrote nothing, or copied, would keep the other array live or
     // be hoisted in front of every op).
     switch (op.pj) {
-    case 0: pair_pj<C64, K, 0, SWAP, CTRL>(in, out, li, op); break;
+    case 0: pair_pj<C64, K, 0, SWAP, CTRL>(in, out, lbase, soff, op); break;
     case 1:
-        if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(in, out, li, op);
+        if constexpr (K > 1) pair_pj<C64, K, 1, SWAP, CTRL>(in, out, lbase, soff, op);
         else __builtin_unreachable();
         break;
     case 2:
-        if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(in, out, li, op);
+        if constexpr (K > 2) pair_pj<C64, K, 2, SWAP, CTRL>(in, out, lbase, soff, op);
         else __builtin_unreachable();
         break;
     case 3:
-        if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(in, out, li, op);
+        if constexpr (K > 3) pair_pj<C64, K, 3, SWAP, CTRL>(in, out, lbase, soff, op);
         else __builtin_unreachable();
         break;
     default: __builtin_unreachable();
@@ -484,7 +491,7 @@ __device__ __forceinline__ void apply_diag_shape(const Amps<C64, K> &in, Amps<C6
 // Applies one op of group G: in -> out.
 template <bool C64, int K>
 __device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &out,
-                                         const uint32_t (&li)[1 << K], COp &op,
+                                         uint32_t lbase, const uint32_t (&soff)[K], COp &op,
                                          const uint64_t *dtab, int L, CGroup &G, uint64_t g,
                                          uint64_t gbase, uint32_t tid, const AmpT<C64> *tab)
 {
@@ -497,12 +504,12 @@ __device__ __forceinline__ void apply_op(const Amps<C64, K> &in, Amps<C64, K> &o
         copy_amps<C64, K>(in, out);   // a control outside the tile is 0 here
     } else if (op.kind == TOP_SWAP) {
         if (op.pk >= 0) apply_rc<C64, K, true>(in, out, op);
-        else if (op.lctrl >= 0 || op.lcm) apply_pair<C64, K, true, true>(in, out, li, op);
-        else apply_pair<C64, K, true, false>(in, out, li, op);
+        else if (op.lctrl >= 0 || op.lcm) apply_pair<C64, K, true, true>(in, out, lbase, soff, op);
+        else apply_pair<C64, K, true, false>(in, out, lbase, soff, op);
     } else {
         if (op.pk >= 0) apply_rc<C64, K, false>(in, out, op);
-        else if (op.lctrl >= 0 || op.lcm) apply_pair<C64, K, false, true>(in, out, li, op);
-        else apply_pair<C64, K, false, false>(in, out, li, op);
+        else if (op.lctrl >= 0 || op.lcm) apply_pair<C64, K, false, true>(in, out, lbase, soff, op);
+        else apply_pair<C64, K, false, false>(in, out, lbase, soff, op);
     }
 }
 
@@ -514,7 +521,8 @@ __device__ __forceinline__ void write_exit(AmpT<C64> *lds, const Amps<C64, K> &v
                                            const uint32_t (&soff)[K], CGroup &G)
 {
     constexpr int NR = 1 << K;
-    const uint32_t sb = lds_slot<C64>(lbase);
+    uint32_t sb = lds_slot<C64>(lbase);
+    asm volatile("" : "+v"(sb));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         uint32_t x = G.xb;
@@ -533,7 +541,8 @@ template <bool C64, int K>
 __device__ __forceinline__ void write_map(AmpT<C64> *lds, const Amps<C64, K> &val, uint32_t lbase,
                                           const uint32_t (&soff)[K], const uint32_t (&xr)[1 << K])
 {
-    const uint32_t sb = lds_slot<C64>(lbase);
+    uint32_t sb = lds_slot<C64>(lbase);
+    asm volatile("" : "+v"(sb));
 #pragma unroll
     for (int r = 0; r < (1 << K); ++r) {
         uint32_t c = 0;
@@ -597,22 +606,12 @@ __device__ __forceinline__ void fetch_direct(const TileArgs &a, uint64_t gb, con
     }
 }
 
-// A group's registers taken from amplitudes fetched in its own layout, with
-// their local indices (as gather gives them).
+// A group's registers taken from amplitudes fetched in its own layout.
 template <bool C64, int K>
-__device__ __forceinline__ void take_regs(const Amps<C64, K> &cur, uint32_t lbase,
-                                          const uint32_t (&soff)[K], uint32_t (&li)[1 << K],
-                                          Amps<C64, K> &v)
+__device__ __forceinline__ void take_regs(const Amps<C64, K> &cur, Amps<C64, K> &v)
 {
 #pragma unroll
-    for (int r = 0; r < (1 << K); ++r) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (r & (1 << k)) c |= soff[k];
-        li[r] = lbase | c;
-        v[r] = cur[r];
-    }
+    for (int r = 0; r < (1 << K); ++r) v[r] = cur[r];
 }
 
 // Register combination r goes to the index of combination xr[r] (the group's
@@ -693,12 +692,14 @@ __device__ __forceinline__ void walk_init(const TileArgs &a, AmpT<C64> *tab, Wal
     for (int k = 0; k < K; ++k) w.pbit[k] = 1u << uint32_t((a.osrc >> (4 * (a.L - K + k))) & 15u);
 }
 
-// Tile g's amplitudes (index bits outside the tile = gbase) from HBM into
-// registers, in the tile-load layout: thread tid holds local indices
-// tid + r W.
-template <bool C64, int K, bool NT>
-__device__ __forceinline__ void tile_fetch(const TileArgs &a, const Walk<K> &w, uint64_t gbase,
-                                           Amps<C64, K> &pv)
+// Tile g (index bits outside the tile = gbase) from HBM into LDS, then a
+// barrier that orders LDS only (the previous tile's global stores may still
+// be in flight). WAIT: the previous tile ended in direct stores, whose last
+// group read other threads' slots, so the slots are written only after a
+// barrier.
+template <bool C64, int K, bool NT, bool WAIT = false>
+__device__ __forceinline__ void tile_load(const TileArgs &a, const Walk<K> &w, uint64_t gbase,
+                                          AmpT<C64> *lds)
 {
     using A = AmpT<C64>;
     constexpr int NR = 1 << K;
@@ -707,25 +708,15 @@ __device__ __forceinline__ void tile_fetch(const TileArgs &a, const Walk<K> &w, 
     // recomputed at each use instead of being hoisted out of the tile loop
     // and held in registers through all the groups.
     uint64_t dtv = w.dt;
-    asm volatile("" : "+v"(dtv));
+    uint32_t tv = w.tid;
+    asm volatile("" : "+v"(dtv), "+v"(tv));
+    A pv[NR];
     if (w.active) {
         uint64_t roff[NR];
         reg_offsets<K>(w.rbit, roff);
 #pragma unroll
         for (int r = 0; r < NR; ++r) pv[r] = ld_amp<NT>(&psi[gbase | dtv | roff[r]]);
     }
-}
-
-// Fetched registers into LDS, then a barrier that orders LDS only (the
-// previous tile's global stores may still be in flight). WAIT: the previous
-// tile ended in direct stores, whose last group read other threads' slots,
-// so the slots are written only after a barrier.
-template <bool C64, int K, bool WAIT = false>
-__device__ __forceinline__ void tile_fill(const Walk<K> &w, const Amps<C64, K> &pv, AmpT<C64> *lds)
-{
-    constexpr int NR = 1 << K;
-    uint32_t tv = w.tid;
-    asm volatile("" : "+v"(tv));
     if constexpr (WAIT) lds_barrier();
     if (w.active) {
 #pragma unroll
@@ -734,14 +725,10 @@ __device__ __forceinline__ void tile_fill(const Walk<K> &w, const Amps<C64, K> &
     lds_barrier();
 }
 
-// The tile-load layout's fetch, as a callable for walk_tiles.
-template <bool C64, int K, bool NT>
-struct TileFetch {
-    const TileArgs &a;
-    __device__ __forceinline__ void operator()(uint64_t gbase, const Walk<K> &w, Amps<C64, K> &pv) const
-    {
-        tile_fetch<C64, K, NT>(a, w, gbase, pv);
-    }
+// The fetch of walks whose first group does not take fetched registers.
+struct NoFetch {
+    template <typename W, typename R>
+    __device__ __forceinline__ void operator()(uint64_t, const W &, R &) const {}
 };
 
 // The tile from LDS back to HBM, in the relabelled order when the pass has
@@ -780,13 +767,12 @@ __device__ __forceinline__ void tile_store(const TileArgs &a, const Walk<K> &w, 
     if (permute) lds_barrier();
 }
 
-// A group's register amplitudes: local slot li[r] of register combination r
-// (the thread's fixed tile bits lbase plus the set bits of r placed at the
-// group's register bits, soff[k] = 1 << s_k), read from LDS.
+// A group's register amplitudes: register combination r holds local index
+// lbase | c(r), the thread's fixed tile bits lbase plus the set bits of r
+// placed at the group's register bits (soff[k] = 1 << s_k), read from LDS.
 template <bool C64, int K>
 __device__ __forceinline__ void gather(const AmpT<C64> *lds, uint32_t lbase,
-                                       const uint32_t (&soff)[K], uint32_t (&li)[1 << K],
-                                       Amps<C64, K> &v)
+                                       const uint32_t (&soff)[K], Amps<C64, K> &v)
 {
     const uint32_t sb = lds_slot<C64>(lbase);
 #pragma unroll
@@ -795,22 +781,22 @@ __device__ __forceinline__ void gather(const AmpT<C64> *lds, uint32_t lbase,
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (r & (1 << k)) c |= soff[k];
-        li[r] = lbase | c;
         v[r] = lds[sb + lds_slot<C64>(c)];
     }
 }
 
 // A group's write-back: to the slots it read, or through its exit map.
 template <bool C64, int K>
-__device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v,
-                                        const uint32_t (&li)[1 << K], uint32_t lbase,
+__device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v, uint32_t lbase,
                                         const uint32_t (&soff)[K], CGroup &G, bool exit_map)
 {
-    (void)li;
     if (exit_map) {
         write_exit<C64, K>(lds, v, lbase, soff, G);
     } else {
-        const uint32_t sb = lds_slot<C64>(lbase);
+        // An opaque base: the slots are recomputed here instead of being
+        // carried in registers from the gather through all the ops.
+        uint32_t sb = lds_slot<C64>(lbase);
+        asm volatile("" : "+v"(sb));
 #pragma unroll
         for (int r = 0; r < (1 << K); ++r) {
             uint32_t c = 0;
@@ -823,13 +809,13 @@ __device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v,
 }
 
 // Processes tiles g = g0, g0 + gstep, ... below gend of the pass `a` with one
-// work-group: each tile is fetched into registers (`fetch`: the tile-load
-// layout, or with DF the first group's own layout), put in LDS (unless DF),
-// `groups(g, gbase, w, regs)` runs the pass's register groups on it (every
-// group ending in a work-group barrier; with DF the first group takes the
-// fetched registers), and it is stored (unless DL: the last group stores it
-// and ends without a barrier). Threads tid >= 2^(L-K) (a tile smaller than
-// the work-group) take part in the barriers only.
+// work-group: each tile is loaded into LDS (with DF instead fetched into
+// registers by `fetch`, in the first group's own layout), `groups(g, gbase,
+// w, regs)` runs the pass's register groups on it (every group ending in a
+// work-group barrier; with DF the first group takes the fetched registers),
+// and it is stored (unless DL: the last group stores it and ends without a
+// barrier). Threads tid >= 2^(L-K) (a tile smaller than the work-group) take
+// part in the barriers only.
 template <bool C64, int K, bool NT, bool DF = false, bool DL = false, typename Groups,
           typename Fetch>
 __device__ __forceinline__ void walk_tiles(const TileArgs &a, uint64_t g0, uint64_t gend,
@@ -843,9 +829,12 @@ __device__ __forceinline__ void walk_tiles(const TileArgs &a, uint64_t g0, uint6
     if constexpr (DF) lds_barrier();
     for (uint64_t g = g0; g < gend; g += gstep) {
         const uint64_t gbase = deposit(g, a.omask);
+        // Only a DF walk fills these registers; loading through them in the
+        // other walks would hold them live and costs the generic kernels
+        // their registers.
         Amps<C64, K> cur;
-        fetch(gbase, w, cur);
-        if constexpr (!DF) tile_fill<C64, K, DL>(w, cur, lds);
+        if constexpr (DF) fetch(gbase, w, cur);
+        else tile_load<C64, K, NT, DL>(a, w, gbase, lds);
         groups(g, gbase, w, cur);
         if constexpr (!DL) tile_store<C64, K, NT>(a, w, gbase, lds);
     }
