@@ -177,7 +177,7 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
         if (first)
             o << "            take_regs<C64, K>(cur, v);\n";
         else
-            o << "            gather<C64, K>(lds, lbase, soff, v);\n";
+            o << "            gather_fixed<C64, K>(lds, lbase, soff, v);\n";
         const char *arr[2] = {"v", "u"};
         for (int oi = 0; oi < G.nops; ++oi) {
             const TileOp &t = ops[G.op0 + oi];
@@ -261,7 +261,7 @@ std::string pass_source(const TileArgs &a, const TileGroup *groups, const TileOp
             for (int r = 0; r < NR; ++r) o << (r ? ", " : "") << exit_of(G, K, r) << "u";
             o << "};\n            write_map<C64, K>(lds, " << fin << ", lbase, soff, xr);\n";
         } else {
-            o << "            scatter<C64, K>(lds, " << fin << ", lbase, soff, G, false);\n";
+            o << "            scatter_fixed<C64, K>(lds, " << fin << ", lbase, soff);\n";
         }
         o << "            __builtin_amdgcn_s_setprio(0);\n"
           << "            lds_barrier();\n"

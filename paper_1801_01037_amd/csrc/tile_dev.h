@@ -521,22 +521,29 @@ __device__ __forceinline__ void write_exit(AmpT<C64> *lds, const Amps<C64, K> &v
                                            const uint32_t (&soff)[K], CGroup &G)
 {
     constexpr int NR = 1 << K;
-    uint32_t sb = lds_slot<C64>(lbase);
-    asm volatile("" : "+v"(sb));
+    uint32_t mb = lbase, ms[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        mb |= ((G.xb >> k) & 1u) ? soff[k] : 0u;
+        uint32_t m = 0;
+        const uint32_t col = G.xs[k];
+#pragma unroll
+        for (int k2 = 0; k2 < K; ++k2) m |= ((col >> k2) & 1u) ? soff[k2] : 0u;
+        ms[k] = m;
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        uint32_t x = G.xb;
+        uint32_t l = mb;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (r & (1 << k)) x ^= G.xs[k];
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) c |= ((x >> k) & 1u) ? soff[k] : 0u;
-        lds[sb + lds_slot<C64>(c)] = val[r];
+            if (r & (1 << k)) l ^= ms[k];
+        lds[lds_slot<C64>(l)] = val[r];
     }
 }
 
-// The same with the map given as a table (a compiled pass: constants).
+// The same with the map given as a table, for register bits fixed at
+// compile time (a compiled pass): the thread's base slot plus a constant
+// offset per register.
 template <bool C64, int K>
 __device__ __forceinline__ void write_map(AmpT<C64> *lds, const Amps<C64, K> &val, uint32_t lbase,
                                           const uint32_t (&soff)[K], const uint32_t (&xr)[1 << K])
@@ -770,9 +777,47 @@ __device__ __forceinline__ void tile_store(const TileArgs &a, const Walk<K> &w, 
 // A group's register amplitudes: register combination r holds local index
 // lbase | c(r), the thread's fixed tile bits lbase plus the set bits of r
 // placed at the group's register bits (soff[k] = 1 << s_k), read from LDS.
+// Register bits known only at run time (the generic kernel): each slot is
+// computed from its full local index.
 template <bool C64, int K>
 __device__ __forceinline__ void gather(const AmpT<C64> *lds, uint32_t lbase,
                                        const uint32_t (&soff)[K], Amps<C64, K> &v)
+{
+#pragma unroll
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) c |= soff[k];
+        v[r] = lds[lds_slot<C64>(lbase | c)];
+    }
+}
+
+// A group's write-back: to the slots it read, or through its exit map.
+template <bool C64, int K>
+__device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v, uint32_t lbase,
+                                        const uint32_t (&soff)[K], CGroup &G, bool exit_map)
+{
+    if (exit_map) {
+        write_exit<C64, K>(lds, v, lbase, soff, G);
+    } else {
+#pragma unroll
+        for (int r = 0; r < (1 << K); ++r) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (r & (1 << k)) c |= soff[k];
+            lds[lds_slot<C64>(lbase | c)] = v[r];
+        }
+    }
+}
+
+// The same two for register bits fixed at compile time (a compiled pass):
+// the thread's base slot plus a constant offset per register, which the
+// LDS instructions take as immediates.
+template <bool C64, int K>
+__device__ __forceinline__ void gather_fixed(const AmpT<C64> *lds, uint32_t lbase,
+                                             const uint32_t (&soff)[K], Amps<C64, K> &v)
 {
     const uint32_t sb = lds_slot<C64>(lbase);
 #pragma unroll
@@ -785,26 +830,21 @@ __device__ __forceinline__ void gather(const AmpT<C64> *lds, uint32_t lbase,
     }
 }
 
-// A group's write-back: to the slots it read, or through its exit map.
 template <bool C64, int K>
-__device__ __forceinline__ void scatter(AmpT<C64> *lds, const Amps<C64, K> &v, uint32_t lbase,
-                                        const uint32_t (&soff)[K], CGroup &G, bool exit_map)
+__device__ __forceinline__ void scatter_fixed(AmpT<C64> *lds, const Amps<C64, K> &v, uint32_t lbase,
+                                              const uint32_t (&soff)[K])
 {
-    if (exit_map) {
-        write_exit<C64, K>(lds, v, lbase, soff, G);
-    } else {
-        // An opaque base: the slots are recomputed here instead of being
-        // carried in registers from the gather through all the ops.
-        uint32_t sb = lds_slot<C64>(lbase);
-        asm volatile("" : "+v"(sb));
+    // An opaque base: the slots are recomputed here instead of being
+    // carried in registers from the gather through all the ops.
+    uint32_t sb = lds_slot<C64>(lbase);
+    asm volatile("" : "+v"(sb));
 #pragma unroll
-        for (int r = 0; r < (1 << K); ++r) {
-            uint32_t c = 0;
+    for (int r = 0; r < (1 << K); ++r) {
+        uint32_t c = 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (r & (1 << k)) c |= soff[k];
-            lds[sb + lds_slot<C64>(c)] = v[r];
-        }
+        for (int k = 0; k < K; ++k)
+            if (r & (1 << k)) c |= soff[k];
+        lds[sb + lds_slot<C64>(c)] = v[r];
     }
 }
 
