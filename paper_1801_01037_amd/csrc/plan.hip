@@ -137,6 +137,8 @@ double op_cost(const POp &op)
     }
 }
 constexpr double kGroupCost = 25.0;   // one LDS exchange of the register amplitudes
+constexpr int kCoverMinQubits = 26;    // states that get the coverage search for groups
+constexpr int kCoverPool = 8;          // qubits its candidate register sets are drawn from
 constexpr double kPassFloor = 415.0;  // a pass's HBM time on the same scale
 
 // spread = false: each block is seeded with the first two-qubit op left;
@@ -494,8 +496,14 @@ void flush_diag(std::map<int, PPivot> &pending, uint64_t qm, std::vector<POp> &o
 // With `spread`, two-qubit blocks are formed over the whole pass first (so a
 // block is not cut where one group's light cone ends) with the spread rule of
 // fuse_group.
+//
+// With `cover`, each group instead takes the register set under which the most
+// op cost can run next: sets of K qubits drawn from the qubits of the first
+// ops left (targets, both qubits of 4x4s, tile controls) are scored by
+// running the light-cone rule with the set fixed, the first-fit set among
+// them, and the best is kept.
 std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::vector<int> &T,
-                                const TileGeom &geo, bool spread)
+                                const TileGeom &geo, bool spread, bool cover = false)
 {
     auto local = [&](int b) { return int(std::lower_bound(T.begin(), T.end(), b) - T.begin()); };
     if (spread) ops = fuse_group(std::move(ops), Pm, true);
@@ -505,11 +513,74 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
         qmask[i] = op_qmask(ops[i]);
         rest[i] = int(i);
     }
+    auto need_of = [&](int i) {
+        const POp &op = ops[i];
+        return op.kind == TOP_U4 ? qmask[i] : uint64_t(1) << op.target;
+    };
+    // Op cost that runs with register set S fixed (the light-cone rule).
+    auto coverage = [&](uint64_t S) {
+        uint64_t blocked = 0;
+        double score = 0;
+        for (int i : rest) {
+            if ((blocked & Pm) == Pm) break;
+            const uint64_t qm = qmask[i];
+            if (qm & blocked) {
+                blocked |= qm;
+                continue;
+            }
+            const POp &op = ops[i];
+            if (op.kind != TOP_DIAG && (need_of(i) & ~S)) {
+                blocked |= qm;
+                continue;
+            }
+            score += op_cost(op);
+        }
+        return score;
+    };
     std::vector<PGroup> groups;
     while (!rest.empty()) {
         PGroup cur;
         uint64_t Sq = 0, blocked = 0;
         later.clear();
+        uint64_t fixed = 0;   // cover: the chosen register set
+        if (cover) {
+            // First-fit set (as below) and the candidate pool.
+            uint64_t ff = 0, pool = 0, blk = 0;
+            for (int i : rest) {
+                const uint64_t qm = qmask[i];
+                if (qm & blk) {
+                    blk |= qm;
+                    continue;
+                }
+                if (ops[i].kind == TOP_DIAG) continue;
+                const uint64_t need = need_of(i);
+                if (__builtin_popcountll(ff | need) <= geo.K) ff |= need;
+                else blk |= qm;
+                uint64_t q = need;
+                if (ops[i].kind != TOP_U4 && ops[i].control >= 0 && ((Pm >> ops[i].control) & 1))
+                    q |= uint64_t(1) << ops[i].control;
+                if (__builtin_popcountll(pool | q) > kCoverPool) break;
+                pool |= q;
+            }
+            fixed = ff;
+            double best = coverage(ff);
+            int pb[64], np = 0;
+            for (int b = 0; b < 64; ++b)
+                if ((pool >> b) & 1) pb[np++] = b;
+            const int want = std::min(geo.K, np);
+            for (uint32_t m = 1; m < (1u << np); ++m) {
+                if (__builtin_popcount(m) != want) continue;
+                uint64_t S = 0;
+                for (int k = 0; k < np; ++k)
+                    if ((m >> k) & 1) S |= uint64_t(1) << pb[k];
+                const double sc = coverage(S);
+                if (sc > best) {
+                    best = sc;
+                    fixed = S;
+                }
+            }
+            Sq = fixed;
+        }
         for (size_t k = 0; k < rest.size(); ++k) {
             const int i = rest[k];
             POp &op = ops[i];
@@ -531,7 +602,13 @@ std::vector<PGroup> make_groups(std::vector<POp> ops, uint64_t Pm, const std::ve
             uint64_t want = need;
             if (op.kind != TOP_U4 && op.control >= 0 && !op.xcm && ((Pm >> op.control) & 1))
                 want |= uint64_t(1) << op.control;
-            if (__builtin_popcountll(Sq | want) <= geo.K) {
+            if (cover) {
+                if (need & ~fixed) {
+                    blocked |= qm;
+                    later.push_back(i);
+                    continue;
+                }
+            } else if (__builtin_popcountll(Sq | want) <= geo.K) {
                 Sq |= want;
             } else if (__builtin_popcountll(Sq | need) <= geo.K) {
                 Sq |= need;
@@ -758,12 +835,24 @@ std::vector<PPass> plan_passes_one(int n, const TileGeom &geo, const std::vector
                 }
             if (!moved) pass.osrc.clear();
         }
-        // Groups, made both ways; the cheaper set is kept.
+        // Groups, made each way; the cheapest set is kept. The coverage
+        // search (fewer groups: 93 -> 72 on the 30-qubit layered circuit,
+        // 2-4 % of its time) costs host time per group, so it runs only for
+        // states whose passes are long enough to repay it.
         {
-            std::vector<PGroup> ga = make_groups(ops, Pm, pass.T, geo, false);
-            if (geo.fuse4 && geo.K >= 2) {
-                std::vector<PGroup> gb = make_groups(std::move(ops), Pm, pass.T, geo, true);
-                if (groups_cost(gb) < groups_cost(ga)) ga.swap(gb);
+            const bool try_cover = n >= kCoverMinQubits;
+            std::vector<PGroup> ga;
+            double best = 0;
+            for (int w = 0; w < 4; ++w) {
+                const bool spread = w & 1, cover = w & 2;
+                if (cover && !try_cover) continue;
+                if (spread && !(geo.fuse4 && geo.K >= 2)) continue;
+                std::vector<PGroup> gw = make_groups(ops, Pm, pass.T, geo, spread, cover);
+                const double c = groups_cost(gw);
+                if (ga.empty() || c < best) {
+                    best = c;
+                    ga.swap(gw);
+                }
             }
             pass.groups = std::move(ga);
         }
