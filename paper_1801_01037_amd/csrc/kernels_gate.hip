@@ -332,12 +332,17 @@ hipError_t launch_pair_u(PairArgs<std::conditional_t<C64, float, double>> a, hip
     // One pair per thread; four when the state has more pairs than a launch
     // holds work-items. Grids that split evenly over the XCDs get the
     // XCD-contiguous order (30-qubit 1q median over targets 5.98 -> 6.20 TB/s).
-    // Pairs whose halves lie 4 GiB or more apart (the strides at which both
-    // halves of a pair fall on the same memory banks) take two neighbouring
-    // chunks per thread, read in 2 KiB runs per wave: 30 qubits, complex64
-    // target 29 5.55 -> 5.79 TB/s, complex128 target 28 5.55 -> 5.84 TB/s
-    // (nearer pairs are faster with one chunk per thread).
-    const bool far = LAYOUT == kSplit && a.tstride * (C64 ? 8 : 16) >= (uint64_t(1) << 32);
+    // Pairs whose halves lie 256 MiB or 4 GiB or more apart take two
+    // neighbouring chunks per thread, read in 2 KiB runs per wave. Both
+    // halves of a pair then fall on the same memory banks (the slow strides
+    // repeat every four address bits from 16 MiB); at these strides the
+    // longer runs were measured faster at 30 qubits: complex128 targets 24
+    // 5.60 -> 5.75 TB/s, 28 5.55 -> 5.84, 29 5.78 -> 5.85; complex64 targets
+    // 25 5.63 -> 5.76, 29 5.56 -> 5.80. At 16 MiB, 32 MiB and 512 MiB and for
+    // nearer pairs one chunk per thread stays faster.
+    const uint64_t stride_bytes = a.tstride * (C64 ? 8 : 16);
+    const bool far = LAYOUT == kSplit &&
+                     (stride_bytes == (uint64_t(1) << 28) || stride_bytes >= (uint64_t(1) << 32));
     const int u = a.items > kMaxLaunchItems ? 4 : (far ? 2 : 1);
     const unsigned grid = grid_for(a.items, kBlock * u);
     a.xcd_span = (grid % 8 == 0 && uint64_t(grid) * kBlock * u == a.items) ? grid / 8 : 0;
