@@ -138,6 +138,20 @@ sv_status sv_destroy(sv_state s);
  * already queued on the old stream. */
 sv_status sv_set_stream(sv_state s, void *hip_stream);
 
+/* Tile geometry of this handle's SV_FUSE runs and of its plans (the tile pass
+ * that applies many gates per sweep of the state; the paper's per-gate sweep,
+ * section State Vector Partitioning, is the special case of one gate per
+ * sweep). tile_qubits: qubits a pass holds, 4..12 (0: the default, 12);
+ * register_qubits: qubits a thread holds in registers per group, 3 or 4 (0:
+ * the default, 4; plans always use 4); low_qubits: index bits every tile
+ * holds, 0..5 (-1: the default, 3 for complex128 and 4 for complex64). All
+ * are clamped to the state's qubit count. A tuning setting: results depend on
+ * it only through the order of rounding (the grouping of gates changes).
+ * Drops the handle's captured SV_GRAPH circuit. SV_EINVAL outside the ranges;
+ * the setting is then unchanged. */
+sv_status sv_set_tile_geometry(sv_state s, int32_t tile_qubits, int32_t register_qubits,
+                               int32_t low_qubits);
+
 /* Device pointer, qubit count and dtype of a handle (any out may be NULL). */
 sv_status sv_info(sv_state s, void **dev_ptr, int *n_qubits, sv_dtype *dtype);
 

@@ -19,6 +19,7 @@ import numpy as np
 __all__ = [
     "SV_C64", "SV_C128", "SV_FUSE", "SV_FUSE_DENSE", "SV_GRAPH", "SV_NO_RELABEL", "SV_JIT", "SVError", "lib",
     "sv_version", "sv_last_error", "sv_create", "sv_wrap", "sv_destroy", "sv_set_stream",
+    "sv_set_tile_geometry",
     "sv_info", "sv_reset", "sv_reset_uniform", "sv_sample_device", "sv_sample_device_noalloc", "sv_apply_1q", "sv_apply_ctrl", "sv_apply_mcu", "sv_apply_unitary", "sv_apply_cphase",
     "sv_run_circuit", "sv_run_circuit_ex", "sv_run_batch", "sv_probs", "sv_probs_device", "sv_norm", "sv_norm_device", "sv_compare",
     "sv_copy_out", "sv_copy_in", "sv_synchronize", "sv_profile", "sv_profile_read",
@@ -71,6 +72,7 @@ _SIGNATURES = {
     "sv_wrap": ([_vp, _int, _int, _vp, ctypes.POINTER(_vp)], _int),
     "sv_destroy": ([_vp], _int),
     "sv_set_stream": ([_vp, _vp], _int),
+    "sv_set_tile_geometry": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], _int),
     "sv_info": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "sv_reset": ([_vp, _u64], _int),
     "sv_apply_1q": ([_vp, _int, _dp], _int),
@@ -175,6 +177,13 @@ def sv_destroy(h: int) -> None:
 
 def sv_set_stream(h: int, stream: int | None) -> None:
     _check(lib().sv_set_stream(h, stream))
+
+
+def sv_set_tile_geometry(h: int, tile_qubits: int = 0, register_qubits: int = 0,
+                         low_qubits: int = -1) -> None:
+    """Tile geometry of the handle's SV_FUSE runs and plans (0 / 0 / -1:
+    defaults; see include/sv.h)."""
+    _check(lib().sv_set_tile_geometry(h, tile_qubits, register_qubits, low_qubits))
 
 
 def sv_info(h: int):
@@ -472,6 +481,10 @@ class StateVector:
 
     def apply_cphase(self, control, target, theta):
         sv_apply_cphase(self.handle, control, target, theta)
+
+    def set_tile_geometry(self, tile_qubits: int = 0, register_qubits: int = 0,
+                          low_qubits: int = -1):
+        sv_set_tile_geometry(self.handle, tile_qubits, register_qubits, low_qubits)
 
     def run(self, gates, flags: int = 0, mats=None):
         sv_run_circuit(self.handle, gates, flags, mats)

@@ -1,9 +1,12 @@
-"""Autotuner of the batched launch configuration.
+"""Autotuners of the batched launch configuration and of the tile geometry.
 
-For a batch of planned circuits it times each candidate (work-groups per CU,
-tiles per task) on the device with HIP events, keeps the fastest, and caches
-the choice in a JSON file keyed by GPU architecture, dtype and a workload tag
-(the SV_TUNE_CACHE environment variable overrides the file's location).
+For a batch of planned circuits `tune_batch` times each candidate
+(work-groups per CU, tiles per task) on the device with HIP events; for one
+circuit on one state `tune_tile_geometry` times each candidate tile geometry
+(tile qubits, register qubits, fixed low qubits; sv_set_tile_geometry) on the
+tile passes. Each keeps the fastest and caches the choice in a JSON file keyed
+by GPU architecture, dtype and a workload tag (the SV_TUNE_CACHE environment
+variable overrides the file's location).
 """
 from __future__ import annotations
 
@@ -71,4 +74,49 @@ def tune_batch(dtype: int, plans, tag: str, stream=None, repeats: int = 2,
     best = tuple(int(x) for x in choice.split("x"))
     cache[key] = {"best": list(best), "times_ms": times}
     _save(cache)
+    return best, times
+
+
+# (tile qubits, register qubits, fixed low qubits); 0 / -1: the default
+TILE_CANDIDATES = ((0, 0, -1), (0, 3, -1), (11, 0, -1), (10, 0, -1), (0, 0, 4), (0, 0, 5))
+
+
+def tune_tile_geometry(st, gates, tag: str, flags: int = sv.SV_FUSE | sv.SV_JIT,
+                       basis_index: int = 0, repeats: int = 2, candidates=TILE_CANDIDATES,
+                       use_cache: bool = True):
+    """Best tile geometry for running `gates` on the StateVector `st` with
+    `flags`, and the per-candidate tile time (ms, the best of `repeats` runs
+    after one warm-up run, which plans and compiles). Leaves the best geometry
+    set on `st`; the state is overwritten (reset to `basis_index` before each
+    run)."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    key = f"{arch}/tile/{'c64' if st.dtype == sv.SV_C64 else 'c128'}/{st.n}/{tag}"
+    cache = _load()
+    if use_cache and key in cache:
+        best = tuple(cache[key]["best"])
+        st.set_tile_geometry(*best)
+        return best, cache[key]["times_ms"]
+    times = {}
+    for cand in candidates:
+        st.set_tile_geometry(*cand)
+        st.reset(basis_index)
+        st.run(gates, flags)                          # warm-up: plan, compile
+        best = float("inf")
+        for _ in range(repeats):
+            st.reset(basis_index)
+            torch.cuda.synchronize()
+            sv.sv_profile(st.handle, True)
+            st.run(gates, flags)
+            torch.cuda.synchronize()
+            sv.sv_profile(st.handle, False)
+            prof = sv.sv_profile_read(st.handle)
+            best = min(best, sum(v["total_ms"] for k, v in prof.items() if k in ("tile", "graph")))
+        times["%d,%d,%d" % cand] = round(best, 3)
+    best_key = min(times, key=times.get)
+    best = tuple(int(x) for x in best_key.split(","))
+    st.set_tile_geometry(*best)
+    if use_cache:
+        cache[key] = {"best": list(best), "times_ms": times}
+        _save(cache)
     return best, times

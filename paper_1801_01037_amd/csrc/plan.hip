@@ -391,7 +391,9 @@ struct TileGeom {
     bool c64;
 };
 
-TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
+// The tile geometry of a state; `s` (optional) carries the overrides set by
+// sv_set_tile_geometry, applied after the environment's tuning overrides.
+TileGeom geometry(int n, sv_dtype dt, int force_k = 0, const sv_state_s *s = nullptr)
 {
     const bool c64 = dt == SV_C64;
     TileGeom g;
@@ -405,6 +407,11 @@ TileGeom geometry(int n, sv_dtype dt, int force_k = 0)
     if (const char *e = std::getenv("SV_TILE_L")) L = std::max(4, std::min(std::atoi(e), L));
     if (const char *e = std::getenv("SV_TILE_K")) K = std::max(3, std::min(std::atoi(e), 4));
     if (const char *e = std::getenv("SV_TILE_NLOW")) nlow = std::atoi(e);
+    if (s) {
+        if (s->tile_L > 0) L = std::min(s->tile_L, L);
+        if (s->tile_K > 0) K = s->tile_K;
+        if (s->tile_nlow >= 0) nlow = s->tile_nlow;
+    }
     g.fuse4 = true;
     if (const char *e = std::getenv("SV_TILE_FUSE4")) g.fuse4 = std::atoi(e) != 0;
     if (force_k > 0) K = force_k;
@@ -1298,7 +1305,7 @@ struct TileRun {
 static sv_status tile_plan(sv_state s, const sv_gate *gates, size_t n_gates, bool relabel,
                            TileRun *r, std::string *err)
 {
-    r->geo = geometry(s->n, s->dt);
+    r->geo = geometry(s->n, s->dt, 0, s);
     std::vector<Item> items;
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));
@@ -1739,7 +1746,7 @@ sv_status plan_create(sv_state s, const sv_gate *gates, size_t n_gates, sv_plan 
         *err = "planned circuits need at least 4 qubits";
         return SV_EINVAL;
     }
-    const TileGeom geo = geometry(s->n, s->dt, 4);
+    const TileGeom geo = geometry(s->n, s->dt, 4, s);
     std::vector<Item> items;
     items.reserve(n_gates);
     for (size_t i = 0; i < n_gates; ++i) items.push_back(classify(gates[i], int(i)));

@@ -322,6 +322,24 @@ sv_status sv_set_stream(sv_state s, void *hip_stream)
     return SV_OK;
 }
 
+sv_status sv_set_tile_geometry(sv_state s, int32_t tile_qubits, int32_t register_qubits,
+                               int32_t low_qubits)
+{
+    if (sv_status st = check_handle(s)) return st;
+    if (tile_qubits != 0 && (tile_qubits < 4 || tile_qubits > svk::kTileL128))
+        return fail(SV_EINVAL, "tile_qubits must be 0 (default) or 4..12");
+    if (register_qubits != 0 && register_qubits != 3 && register_qubits != 4)
+        return fail(SV_EINVAL, "register_qubits must be 0 (default), 3 or 4");
+    if (low_qubits < -1 || low_qubits > 5)
+        return fail(SV_EINVAL, "low_qubits must be -1 (default) or 0..5");
+    // A captured circuit graph holds launches planned with the old geometry.
+    svk::circuit_graph_release(s);
+    s->tile_L = tile_qubits;
+    s->tile_K = register_qubits;
+    s->tile_nlow = low_qubits;
+    return SV_OK;
+}
+
 sv_status sv_info(sv_state s, void **dev_ptr, int *n_qubits, sv_dtype *dtype)
 {
     if (sv_status st = check_handle(s)) return st;

@@ -173,6 +173,9 @@ struct sv_state_s {
     svk::Profiler prof;
     void *plan = nullptr;             // planner buffers (plan.hip)
     void *graph = nullptr;            // captured circuit graph (graph.hip)
+    // Tile geometry of SV_FUSE runs and plans (sv_set_tile_geometry): tile
+    // qubits, register qubits, fixed low index bits; 0 / 0 / -1: defaults.
+    int tile_L = 0, tile_K = 0, tile_nlow = -1;
 };
 
 namespace svk {

@@ -49,6 +49,7 @@ def test_rejects_bad_arguments_without_a_device(lib):
     assert lib.sv_wrap(None, 10, sv.SV_C64, None, ctypes.byref(h)) == sv.SV_EINVAL
     assert lib.sv_wrap(8, 10, sv.SV_C64, None, ctypes.byref(h)) == sv.SV_EINVAL  # misaligned
     assert lib.sv_destroy(None) == sv.SV_OK
+    assert lib.sv_set_tile_geometry(None, 0, 0, -1) == sv.SV_EINVAL
     assert lib.sv_reset(None, 0) == sv.SV_EINVAL
     assert lib.sv_run_circuit(None, None, 1, 0) == sv.SV_EINVAL
     assert lib.sv_run_batch(None, None, None, 1, 0) == sv.SV_EINVAL
