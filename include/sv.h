@@ -144,8 +144,11 @@ sv_status sv_set_stream(sv_state s, void *hip_stream);
  * sweep). tile_qubits: qubits a pass holds, 4..12 (0: the default, 12);
  * register_qubits: qubits a thread holds in registers per group, 3 or 4 (0:
  * the default, 4; plans always use 4); low_qubits: index bits every tile
- * holds, 0..5 (-1: the default, 3 for complex128 and 4 for complex64). All
- * are clamped to the state's qubit count. A tuning setting: results depend on
+ * holds, 0..11 (-1: the default, 3 for complex128 and 4 for complex64; for a
+ * state larger than the 256 MiB last-level cache the planner also plans with 6
+ * and keeps that plan when it needs no more passes, for longer contiguous
+ * runs). All are clamped to the state's qubit count (low_qubits to the tile
+ * width minus one). A tuning setting: results depend on
  * it only through the order of rounding (the grouping of gates changes).
  * Drops the handle's captured SV_GRAPH circuit. SV_EINVAL outside the ranges;
  * the setting is then unchanged. */

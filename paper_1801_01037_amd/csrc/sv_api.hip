@@ -330,8 +330,8 @@ sv_status sv_set_tile_geometry(sv_state s, int32_t tile_qubits, int32_t register
         return fail(SV_EINVAL, "tile_qubits must be 0 (default) or 4..12");
     if (register_qubits != 0 && register_qubits != 3 && register_qubits != 4)
         return fail(SV_EINVAL, "register_qubits must be 0 (default), 3 or 4");
-    if (low_qubits < -1 || low_qubits > 5)
-        return fail(SV_EINVAL, "low_qubits must be -1 (default) or 0..5");
+    if (low_qubits < -1 || low_qubits > 11)
+        return fail(SV_EINVAL, "low_qubits must be -1 (default) or 0..11");
     // A captured circuit graph holds launches planned with the old geometry.
     svk::circuit_graph_release(s);
     s->tile_L = tile_qubits;

@@ -45,7 +45,7 @@ def test_bad_geometries_are_rejected_and_leave_the_setting():
     h = sv.sv_create(n, sv.SV_C128)
     try:
         sv.sv_set_tile_geometry(h, 8, 3, 2)
-        for bad in ((13, 0, -1), (3, 0, -1), (0, 2, -1), (0, 5, -1), (0, 0, 6), (0, 0, -2)):
+        for bad in ((13, 0, -1), (3, 0, -1), (0, 2, -1), (0, 5, -1), (0, 0, 12), (0, 0, -2)):
             with pytest.raises(sv.SVError) as e:
                 sv.sv_set_tile_geometry(h, *bad)
             assert e.value.status == sv.SV_EINVAL

@@ -224,12 +224,14 @@ def test_no_relabel_needs_fuse():
 
 @pytest.mark.parametrize("dtype,shape", [
     (sv.SV_C128, {"qft": (3, 9, 59), "layers": (16, 72, 361)}),
-    (sv.SV_C64, {"qft": (4, 8, 59), "layers": (18, 70, 365)}),
+    (sv.SV_C64, {"qft": (4, 9, 59), "layers": (17, 68, 345)}),
 ], ids=["c128", "c64"])
 def test_benchmark_plans_do_not_grow(dtype, shape):
     """The plans of the 30-qubit benchmark step (QFT, depth-20 layers) keep
     at most the passes, register groups and ops they have now: a planner
-    change that makes them longer shows here before it shows in the timings."""
+    change that makes them longer shows here before it shows in the timings.
+    (Complex64 takes the plans with six fixed low bits: as many or fewer
+    passes, runs of 512 B; the QFT has one group more than with four.)"""
     for name, g in (("qft", qc.qft_circuit(30)), ("layers", qc.layer_circuit(30, 20, 1))):
         _, passes, groups, ops = sv.sv_plan_inspect(30, dtype, g, sv.SV_FUSE)
         p0, g0, o0 = shape[name]
