@@ -221,7 +221,9 @@ def precision_errors(sv, torch, n, flags):
 
 
 # The sources of each kernel class (a change in any invalidates its counters).
-KERNEL_SOURCE = {"tile": ("kernels_tile.hip", "tile_dev.h", "jit.hip"),
+# The tile passes also depend on the planner, which decides what each pass
+# reads and writes.
+KERNEL_SOURCE = {"tile": ("kernels_tile.hip", "tile_dev.h", "jit.hip", "plan.hip"),
                  "pair": ("kernels_gate.hip",), "pair_ctrl": ("kernels_gate.hip",),
                  "swap": ("kernels_gate.hip",), "diag": ("kernels_gate.hip",),
                  "dense": ("kernels_dense.hip",)}

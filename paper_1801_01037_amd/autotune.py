@@ -78,7 +78,7 @@ def tune_batch(dtype: int, plans, tag: str, stream=None, repeats: int = 2,
 
 
 # (tile qubits, register qubits, fixed low qubits); 0 / -1: the default
-TILE_CANDIDATES = ((0, 0, -1), (0, 3, -1), (11, 0, -1), (10, 0, -1), (0, 0, 4), (0, 0, 5))
+TILE_CANDIDATES = ((0, 0, -1), (0, 3, -1), (11, 0, -1), (10, 0, -1), (0, 0, 3), (0, 0, 4), (0, 0, 6))
 
 
 def tune_tile_geometry(st, gates, tag: str, flags: int = sv.SV_FUSE | sv.SV_JIT,
