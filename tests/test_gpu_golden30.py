@@ -9,7 +9,8 @@ QFT of a seeded basis state (465 gates). It holds the amplitudes at 69,000+
 seeded indices (random ones, the first 4,096 and a few special ones), the
 probabilities of the first 2^16 indices and the norm. Every execution path of
 the library runs the same circuits here: gate by gate, fused tile passes with
-and without relabelled storage, and dense 5-qubit blocks; both precisions.
+and without relabelled storage (and with each pass compiled for its own
+program, the benchmark's path), and dense 5-qubit blocks; both precisions.
 
 Bounds: complex128 max-abs <= 1e-12 per amplitude; complex64 relative 2-norm
 error over the sampled amplitudes <= 8 sqrt(G) 2^-24, G the gates applied.
@@ -26,8 +27,8 @@ from tests.gpu_helpers import C128_MAX_ABS, c64_rel_tol
 pytestmark = pytest.mark.gpu
 
 FIXTURE = os.path.join(GOLDEN, "layers30_qft30.npz")
-MODES = [0, sv.SV_FUSE, sv.SV_FUSE | sv.SV_NO_RELABEL, sv.SV_FUSE_DENSE]
-MODE_IDS = ["per-gate", "fused", "fused-standard-order", "dense"]
+MODES = [0, sv.SV_FUSE, sv.SV_FUSE | sv.SV_JIT, sv.SV_FUSE | sv.SV_NO_RELABEL, sv.SV_FUSE_DENSE]
+MODE_IDS = ["per-gate", "fused", "fused-compiled", "fused-standard-order", "dense"]
 
 
 @pytest.fixture(scope="module")
