@@ -86,9 +86,9 @@ def tune_tile_geometry(st, gates, tag: str, flags: int = sv.SV_FUSE | sv.SV_JIT,
                        use_cache: bool = True):
     """Best tile geometry for running `gates` on the StateVector `st` with
     `flags`, and the per-candidate tile time (ms, the best of `repeats` runs
-    after one warm-up run, which plans and compiles). Leaves the best geometry
-    set on `st`; the state is overwritten (reset to `basis_index` before each
-    run)."""
+    after one warm-up run, which plans and compiles). Candidates the planner
+    cannot place the gates in are skipped. Leaves the best geometry set on
+    `st`; the state is overwritten (reset to `basis_index` before each run)."""
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     key = f"{arch}/tile/{'c64' if st.dtype == sv.SV_C64 else 'c128'}/{st.n}/{tag}"
@@ -101,7 +101,14 @@ def tune_tile_geometry(st, gates, tag: str, flags: int = sv.SV_FUSE | sv.SV_JIT,
     for cand in candidates:
         st.set_tile_geometry(*cand)
         st.reset(basis_index)
-        st.run(gates, flags)                          # warm-up: plan, compile
+        try:
+            st.run(gates, flags)                      # warm-up: plan, compile
+        except sv.SVError as e:
+            # a geometry the planner cannot place every gate in (a gate with
+            # more qubits than the tile holds) is skipped
+            if e.status != sv.SV_EUNSUPPORTED:
+                raise
+            continue
         best = float("inf")
         for _ in range(repeats):
             st.reset(basis_index)
@@ -113,6 +120,9 @@ def tune_tile_geometry(st, gates, tag: str, flags: int = sv.SV_FUSE | sv.SV_JIT,
             prof = sv.sv_profile_read(st.handle)
             best = min(best, sum(v["total_ms"] for k, v in prof.items() if k in ("tile", "graph")))
         times["%d,%d,%d" % cand] = round(best, 3)
+    if not times:
+        st.set_tile_geometry(0, 0, -1)
+        raise sv.SVError(sv.SV_EUNSUPPORTED, "no candidate geometry can run these gates")
     best_key = min(times, key=times.get)
     best = tuple(int(x) for x in best_key.split(","))
     st.set_tile_geometry(*best)
