@@ -17,7 +17,7 @@ from tests.test_plan import mixed_circuit
 
 pytestmark = pytest.mark.gpu
 
-GEOMETRIES = [(0, 0, -1), (10, 3, -1), (8, 4, 2), (12, 4, 5), (6, 3, 0)]
+GEOMETRIES = [(0, 0, -1), (10, 3, -1), (8, 4, 2), (12, 4, 5), (12, 4, 6), (6, 3, 0)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
