@@ -49,7 +49,7 @@ def test_one_qubit_gate_every_target(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=DTYPE_IDS)
-@pytest.mark.parametrize("n", [2, 3, 7])
+@pytest.mark.parametrize("n", [2, 3, 7, 9])
 def test_controlled_gate_every_pair(dtype, n):
     psi0 = rounded(qc.random_state(n, 2000 + n), dtype)
     mats = qc.haar_su2(77, n * n)
@@ -202,10 +202,11 @@ def test_torch_wrapped_state_matches_owned_state():
 @pytest.mark.parametrize("dtype,n", [(sv.SV_C128, 25), (sv.SV_C64, 26)], ids=["c128-25", "c64-26"])
 def test_streamed_state_every_pair_layout(dtype, n):
     """A state past the last-level cache (512 MiB) takes the streaming
-    accesses; targets inside a 128-byte line take the lane exchange, targets
-    16 MiB or more apart four pairs per thread, and controls inside a line are
-    tested per amplitude, as are phases on bits inside a line. One sequence
-    covers each, against the oracle."""
+    accesses; targets whose pairs lie within one wave's 64 chunks take the
+    lane exchange (unless a control inserted into the work index lies below
+    the target), targets 16 MiB or more apart two or four pairs per thread,
+    and controls inside a line are tested per amplitude, as are phases on
+    bits inside a line. One sequence covers each, against the oracle."""
     def phase(theta):
         return (1.0, 0.0, 0.0, 0.0, 0.0, 0.0, math.cos(theta), math.sin(theta))
 
@@ -217,7 +218,8 @@ def test_streamed_state_every_pair_layout(dtype, n):
            ((0,), 3, mats[9]), ((1, n - 2), 3, mats[10]), ((0, 1, 2), n - 1, qc.X_MATRIX),
            ((3, 20), 0, qc.X_MATRIX), ((0, 5), 2, mats[11]),
            ((0,), n - 1, phase(0.3)), ((14,), 15, phase(0.5)), ((2,), 5, phase(0.7)),
-           ((0, 1), 2, phase(1.1))]
+           ((0, 1), 2, phase(1.1)), ((), 5, mats[12]), ((), 6, mats[13]), ((4,), 5, mats[14]),
+           ((7,), 5, mats[15]), ((9, 1), 6, qc.X_MATRIX)]
     h = state_from_host(n, dtype, psi0)
     try:
         for controls, t, m in seq:
