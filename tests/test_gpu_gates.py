@@ -219,7 +219,8 @@ def test_streamed_state_every_pair_layout(dtype, n):
            ((3, 20), 0, qc.X_MATRIX), ((0, 5), 2, mats[11]),
            ((0,), n - 1, phase(0.3)), ((14,), 15, phase(0.5)), ((2,), 5, phase(0.7)),
            ((0, 1), 2, phase(1.1)), ((), 5, mats[12]), ((), 6, mats[13]), ((4,), 5, mats[14]),
-           ((7,), 5, mats[15]), ((9, 1), 6, qc.X_MATRIX)]
+           ((7,), 5, mats[15]), ((9, 1), 6, qc.X_MATRIX), ((), 7, mats[0]), ((), 9, mats[1]),
+           ((), 10, mats[2]), ((8,), 7, mats[3]), ((6,), 8, mats[4]), ((12, 0), 9, mats[5])]
     h = state_from_host(n, dtype, psi0)
     try:
         for controls, t, m in seq:
