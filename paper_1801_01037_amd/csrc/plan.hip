@@ -2003,6 +2003,8 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
     // (512-circuit batch, rounds per level 0.5 / 0.75 / 1 / 1.5 / 2 / 4:
     // makespan 915 / 827 / 790 / 815 / 824 / 842 ms, p50 9.8 / 9.8 / 10.0 /
     // 12.1 / 13.0 / 17.1 ms, p99 847 / 776 / 730 / 703 / 712 / 730 ms.)
+    // Levels alone, with no persistent launch or third stream to fill the
+    // gaps between them, take two rounds (makespan 882 ms against 980 ms).
     std::vector<BatchTask> tasks;
     img.level0.clear();
     img.task_circ.clear();
@@ -2012,8 +2014,9 @@ sv_status prepare_batch(sv_batch b, BatchImage &img, const sv_plan *plans,
             const TileArgs &p0 = passes[pass0[i]];
             amps[i] = p0.ntiles << p0.L;
         }
+    const uint64_t rounds = (b->persist_tiles > 0 || b->solo_tiles > 0) ? 1 : 2;
     const uint64_t cap = uint64_t(device_cus()) * uint64_t(std::max(1, b->blocks_per_cu)) *
-                         uint64_t(b->tiles_per_task) * (uint64_t(1) << 12);
+                         uint64_t(b->tiles_per_task) * rounds * (uint64_t(1) << 12);
     std::vector<int32_t> done(count, 0);
     // Small circuits go whole to the persistent launch, least work first.
     std::vector<PersistCircuit> circs;
